@@ -1,0 +1,299 @@
+"""Oracle -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow FP64 CPU reference for the PLV hot path, used by ``tests/``, by
+``__graft_entry__.smoke()`` and by the CPU-baseline leg of ``bench.py``, and by
+nothing else.  It shares no code with the HIP library: the arithmetic lives in
+``plv_oracle.c`` (built with gcc, no fast-math) and this module only marshals
+numpy arrays.
+
+What is computed, and where it comes from in the paper (Bruna, Maestu, Pereda,
+"Phase Locking Value revisited"):
+
+* ``analytic``      Eq. 3: the (band-pass) analytic signal, as the DFT-domain
+                    construction with one-sided weights, by plain DFT sums.
+* ``phase``         Eq. 3 / Appendix, first listing: angle of z (0 at z = 0).
+* ``pair_means``    Eq. 2 per pair, the original formulation: the mean over
+                    samples of exp(i * phase difference).
+* ``metrics``       PLV = |G| (Eq. 2), iPLV = |Im G| (Eq. 13) and
+                    ciPLV = |Im G| / sqrt(1 - Re^2) (Eq. 14).
+* ``full_*``        all pairs assembled into N x N matrices (mirror, diagonal
+                    PLV = 1, iPLV = ciPLV = 0), as the Appendix's matrix forms
+                    return them.
+* ``grad_*``        gradient of a loss on the metrics, in angle space (not in
+                    the paper; it checks the library's adjoint).
+
+Readings of the paper that the oracle takes (orientation of G, absolute
+iPLV/ciPLV, the 1/T normaliser, the z = 0 rule, the ciPLV radicand) are listed
+in the repository's design notes.  Every function here is pinned by the
+``-m "not gpu"`` tests to closed forms, library routines or brute force.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "plv_oracle.c")
+_SO = os.path.join(_HERE, "_plv_oracle.so")
+_LIB = None
+_LOCK = threading.Lock()
+
+_D = C.POINTER(C.c_double)
+_I = C.POINTER(C.c_int64)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C source into ``oracle/_plv_oracle.so`` with gcc."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+               "-pthread", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _LIB
+    with _LOCK:
+        if _LIB is None:
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = C.CDLL(_SO)
+            L.oracle_mask_plain.argtypes = [C.c_int64, _D]
+            L.oracle_mask_band.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, _D]
+            L.oracle_spectral_filter.argtypes = [_D, _D, C.c_int64, C.c_int64, C.c_int64, _D, _D, _D,
+                                                 C.c_int64, C.c_int]
+            L.oracle_spectral_filter.restype = C.c_int
+            L.oracle_phase.argtypes = [_D, _D, C.c_int64, _D]
+            L.oracle_pair_means.argtypes = [_D, C.c_int64, C.c_int64, _I, _I, C.c_int64, _D, _D, C.c_int]
+            L.oracle_metrics.argtypes = [_D, _D, C.c_int64, _D, _D, _D]
+            L.oracle_metric_adjoint.argtypes = [_D, _D, _D, _D, _D, C.c_int64, _D, _D]
+            L.oracle_phase_grad.argtypes = [_D, C.c_int64, C.c_int64, C.c_int64, _D, _D, _D, C.c_int64,
+                                            C.c_int]
+            L.oracle_phase_to_z.argtypes = [_D, _D, _D, C.c_int64, _D, _D]
+            _LIB = L
+    return _LIB
+
+
+def threads() -> int:
+    """Host threads the oracle uses: the cores this process may run on."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return max(1, os.cpu_count() or 1)
+
+
+def _p(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------
+# spectral weights and the analytic signal (Eq. 3)
+# --------------------------------------------------------------------------
+
+def mask_plain(t: int) -> np.ndarray:
+    h = np.empty(int(t), dtype=np.float64)
+    lib().oracle_mask_plain(int(t), _p(h))
+    return h
+
+
+def mask_band(t: int, fs: float, flo: float, fhi: float) -> np.ndarray:
+    h = np.empty(int(t), dtype=np.float64)
+    lib().oracle_mask_band(int(t), float(fs), float(flo), float(fhi), _p(h))
+    return h
+
+
+def spectral_filter(x: np.ndarray, h: np.ndarray, nthreads: int | None = None) -> np.ndarray:
+    """IDFT(h .* DFT(x)) for every row of x (real or complex), by plain DFT sums."""
+    x = np.atleast_2d(x)
+    n, t = x.shape
+    h = _f64(h)
+    assert h.shape == (t,)
+    if np.iscomplexobj(x):
+        xr, xi = _f64(x.real), _f64(x.imag)
+        pxi = _p(xi)
+    else:
+        xr, xi = _f64(x), None
+        pxi = None
+    zr = np.empty((n, t), dtype=np.float64)
+    zi = np.empty((n, t), dtype=np.float64)
+    rc = lib().oracle_spectral_filter(_p(xr), pxi, t, n, t, _p(h), _p(zr), _p(zi), t,
+                                      int(nthreads or threads()))
+    if rc:
+        raise MemoryError("oracle_spectral_filter failed")
+    return zr + 1j * zi
+
+
+def analytic(x: np.ndarray, fs: float | None = None, band=None, nthreads=None) -> np.ndarray:
+    """Analytic signal of each real row: plain one-sided weights, or the
+    band-pass weights of ``band = (flo, fhi)`` in Hz (needs ``fs``)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    t = x.shape[1]
+    h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
+    return spectral_filter(x, h, nthreads)
+
+
+# --------------------------------------------------------------------------
+# phase, per-pair means (Eq. 2) and metrics (Eqs. 13, 14)
+# --------------------------------------------------------------------------
+
+def phase(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z)
+    zr, zi = _f64(z.real), _f64(z.imag)
+    phi = np.empty(zr.shape, dtype=np.float64)
+    lib().oracle_phase(_p(zr), _p(zi), zr.size, _p(phi))
+    return phi
+
+
+def pair_means(phi: np.ndarray, pairs: np.ndarray, nthreads: int | None = None) -> np.ndarray:
+    """G_p = (1/T) sum_t exp(i(phi_a(t) - phi_b(t))) for (a, b) = pairs[p]."""
+    phi = _f64(phi)
+    pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    pi = np.ascontiguousarray(pairs[:, 0])
+    pj = np.ascontiguousarray(pairs[:, 1])
+    n, t = phi.shape
+    assert pairs.size == 0 or (pairs.min() >= 0 and pairs.max() < n)
+    gre = np.empty(len(pairs))
+    gim = np.empty(len(pairs))
+    lib().oracle_pair_means(_p(phi), t, t, pi.ctypes.data_as(_I), pj.ctypes.data_as(_I), len(pairs),
+                            _p(gre), _p(gim), int(nthreads or threads()))
+    return gre + 1j * gim
+
+
+def metrics(g: np.ndarray):
+    """(plv, iplv, ciplv) from complex G values, element-wise."""
+    g = np.asarray(g)
+    gr, gi = _f64(g.real), _f64(g.imag)
+    p = np.empty(gr.shape)
+    i_ = np.empty(gr.shape)
+    c = np.empty(gr.shape)
+    lib().oracle_metrics(_p(gr), _p(gi), gr.size, _p(p), _p(i_), _p(c))
+    return p, i_, c
+
+
+def upper_pairs(n: int) -> np.ndarray:
+    iu, ju = np.triu_indices(n, k=1)
+    return np.stack([iu, ju], axis=1).astype(np.int64)
+
+
+def full_from_phase(phi: np.ndarray, nthreads=None) -> dict:
+    """All pairs of [N, T] phases assembled into N x N matrices.
+
+    G_ij for i < j from Eq. 2, G_ji = conj(G_ij), G_ii = 1; PLV, iPLV and ciPLV
+    symmetric with diagonal 1, 0, 0.
+    """
+    n = phi.shape[0]
+    pr = upper_pairs(n)
+    g = pair_means(phi, pr, nthreads)
+    p, i_, c = metrics(g)
+    G = np.eye(n, dtype=np.complex128)
+    P = np.eye(n)
+    I = np.zeros((n, n))
+    Cc = np.zeros((n, n))
+    a, b = pr[:, 0], pr[:, 1]
+    G[a, b] = g
+    G[b, a] = np.conj(g)
+    for M, v in ((P, p), (I, i_), (Cc, c)):
+        M[a, b] = v
+        M[b, a] = v
+    return {"g": G, "plv": P, "iplv": I, "ciplv": Cc}
+
+
+def full_from_analytic(z: np.ndarray, window=None, nthreads=None) -> dict:
+    z = np.atleast_2d(z)
+    if window is not None:
+        z = z[:, window[0]:window[1]]
+    return full_from_phase(phase(z), nthreads)
+
+
+def full_from_real(x: np.ndarray, fs: float | None = None, band=None, window=None, nthreads=None) -> dict:
+    return full_from_analytic(analytic(x, fs, band, nthreads), window, nthreads)
+
+
+def pairs_from_analytic(z: np.ndarray, pairs: np.ndarray, window=None, nthreads=None) -> np.ndarray:
+    """G for selected pairs only (rows are independent, so only the rows the
+    pairs touch are needed)."""
+    z = np.atleast_2d(z)
+    if window is not None:
+        z = z[:, window[0]:window[1]]
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    rows, inv = np.unique(pairs.reshape(-1), return_inverse=True)
+    phi = phase(np.asarray(z[rows]))
+    return pair_means(phi, inv.reshape(-1, 2), nthreads)
+
+
+# --------------------------------------------------------------------------
+# gradient (angle space)
+# --------------------------------------------------------------------------
+
+def _pair_upstream(gp, gi, gc, n):
+    """Combine dL/d(output) given as full N x N matrices over (i, j) and (j, i);
+    the diagonal is ignored.  Returns upper-triangle arrays (zero elsewhere)."""
+    out = []
+    mask = np.triu(np.ones((n, n), dtype=bool), k=1)
+    for gmat in (gp, gi, gc):
+        if gmat is None:
+            out.append(None)
+            continue
+        gmat = _f64(gmat).reshape(n, n)
+        s = gmat + gmat.T
+        out.append(np.where(mask, s, 0.0))
+    return out
+
+
+def grad_phase(phi: np.ndarray, gp=None, gi=None, gc=None, g_full=None, nthreads=None) -> np.ndarray:
+    """dL/dphi [N, T] for upstream gradients on the N x N metric matrices."""
+    phi = _f64(phi)
+    n, t = phi.shape
+    G = g_full if g_full is not None else full_from_phase(phi, nthreads)["g"]
+    upp, upi, upc = _pair_upstream(gp, gi, gc, n)
+    gr, gim = _f64(G.real), _f64(G.imag)
+    dre = np.zeros((n, n))
+    dim = np.zeros((n, n))
+    z = np.zeros((n, n))
+    lib().oracle_metric_adjoint(_p(gr), _p(gim), _p(upp if upp is not None else z),
+                                _p(upi if upi is not None else z), _p(upc if upc is not None else z),
+                                n * n, _p(dre), _p(dim))
+    dphi = np.empty((n, t))
+    lib().oracle_phase_grad(_p(phi), t, n, t, _p(dre), _p(dim), _p(dphi), t, int(nthreads or threads()))
+    return dphi
+
+
+def grad_from_analytic(z: np.ndarray, gp=None, gi=None, gc=None, window=None, nthreads=None) -> np.ndarray:
+    """dL/dRe z + i dL/dIm z, [N, T]."""
+    z = np.atleast_2d(np.asarray(z, dtype=np.complex128))
+    n, t = z.shape
+    w0, w1 = (0, t) if window is None else window
+    zw = np.ascontiguousarray(z[:, w0:w1])
+    dphi = grad_phase(phase(zw), gp, gi, gc, nthreads=nthreads)
+    zr, zi = _f64(zw.real), _f64(zw.imag)
+    dzr = np.empty(zr.shape)
+    dzi = np.empty(zr.shape)
+    lib().oracle_phase_to_z(_p(zr), _p(zi), _p(dphi), zr.size, _p(dzr), _p(dzi))
+    out = np.zeros((n, t), dtype=np.complex128)
+    out[:, w0:w1] = dzr + 1j * dzi
+    return out
+
+
+def grad_from_real(x: np.ndarray, fs=None, band=None, gp=None, gi=None, gc=None, window=None,
+                   nthreads=None) -> np.ndarray:
+    """dL/dx [N, T] through the analytic-signal map z = M x.
+
+    M = IDFT diag(h) DFT is Hermitian for real h, so dL/dx = Re(M zbar) with
+    zbar = dL/dRe z + i dL/dIm z.
+    """
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    t = x.shape[1]
+    h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
+    z = spectral_filter(x, h, nthreads)
+    zbar = grad_from_analytic(z, gp, gi, gc, window, nthreads)
+    return spectral_filter(zbar, h, nthreads).real
