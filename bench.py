@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""PLV / iPLV / ciPLV throughput on one MI355X.
+
+Workload (sensor/ROI scale): N = 1024 analytic signals of T = 60000 samples
+(60 s at 1 kHz) as complex64 [N, T], from the seeded lagged-oscillator
+generator with 32 latent 8-12 Hz oscillators, zero-lag mixing 0.3 on channel
+pairs and N(0, 0.5) noise.  One step = one plv_from_analytic call: phasor
+normalisation, the upper-triangle Gram on MFMA, the chunk sum and the fused
+PLV/iPLV/ciPLV epilogue with mirrored stores, inputs already in HBM.
+
+value = pair-samples/s of the split-BF16 path, pair-samples = N(N-1)/2 * T.
+The plain FP32 path runs on the same input for comparison, and both are
+checked against the FP64 oracle on a sample of pairs (in the CPU-baseline
+leg, which also times the oracle).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PLV/ciPLV pair-samples/s + %MFMA peak, split-BF16 vs FP32 at stated err"
+PEAK_TFLOPS = {"split_bf16": 2500.0, "bf16": 2500.0, "f16": 2500.0, "f32": 157.3, "f64": 78.6}
+# MFMA flops the contraction performs per pair-sample: one complex
+# multiply-add is 4 real multiply-adds (8 flops); the split form does three.
+FLOP_PER_PAIR_SAMPLE = {"split_bf16": 24, "bf16": 8, "f16": 8, "f32": 8, "f64": 8}
+N_SIG, T_SAMP, FS = 1024, 60000, 1000.0
+
+
+def run_gpu(z, prec, steps, warmup):
+    import torch
+
+    import paper_1710_08037_amd as plv
+
+    for _ in range(warmup):
+        plv.from_analytic(z, prec=prec)
+    torch.cuda.synchronize()
+    plv.timing_enable(True)
+    plv.timing_read(reset=True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        plv.from_analytic(z, prec=prec)
+    stop.record()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    stages = plv.timing_read(reset=True)
+    plv.timing_enable(False)
+    return total_ms / steps, stages
+
+
+def roofline(prec, n, t, stages):
+    ms, calls, launches = stages["gram"]
+    per_launch_s = ms / max(launches, 1) / 1e3
+    flops = FLOP_PER_PAIR_SAMPLE[prec] * (n * (n - 1) // 2) * t
+    achieved = flops / per_launch_s / 1e12
+    peak = PEAK_TFLOPS[prec]
+    return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "herk_kernel<%s>" % prec, "kernel_ms": round(per_launch_s * 1e3, 4),
+            "flop_per_pair_sample": FLOP_PER_PAIR_SAMPLE[prec]}
+
+
+def cpu_baseline(z_np, gpu_out, budget_s=15.0):
+    """Time the FP64 oracle (per-pair angle / exp / mean) on all pairs among
+    the first R rows of the same input, R sized for about `budget_s`, and
+    check the GPU results on exactly those pairs."""
+    import numpy as np
+
+    import oracle
+
+    nthreads = oracle.threads()
+    t = z_np.shape[1]
+
+    def run(r):
+        zs = z_np[:r].astype(np.complex128)
+        pr = oracle.upper_pairs(r)
+        t0 = time.perf_counter()
+        phi = oracle.phase(zs)
+        g = oracle.pair_means(phi, pr, nthreads)
+        dt = time.perf_counter() - t0
+        return g, pr, dt
+
+    g, pr, dt = run(32)
+    rate = len(pr) * t / dt
+    want_pairs = rate * budget_s / t
+    r = int(min(z_np.shape[0], max(32, math.sqrt(2 * want_pairs))))
+    g, pr, dt = run(r)
+    value = len(pr) * t / dt
+    p, ip, cp = oracle.metrics(g)
+    errs = {}
+    for prec, out in gpu_out.items():
+        a, b = pr[:, 0], pr[:, 1]
+        gg = out["g"][a, b]
+        e = max(np.abs(gg.real - g.real).max(), np.abs(gg.imag - g.imag).max())
+        errs[prec] = {"g": float(e),
+                      "plv": float(np.abs(out["plv"][a, b] - p).max()),
+                      "iplv": float(np.abs(out["iplv"][a, b] - ip).max()),
+                      "ciplv": float(np.abs(out["ciplv"][a, b] - cp).max())}
+    base = {"value": round(value, 1), "unit": "pair-samples/s", "cores": nthreads, "kind": "oracle",
+            "sample": "all %d pairs among the first %d signals x %d samples of the same input, %.1f s"
+                      % (len(pr), r, t, dt)}
+    return base, errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the path runs on a single MI355X (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+
+    torch.cuda.set_device(0)
+    z_np = synth.glag_analytic(N_SIG, T_SAMP, FS, 32, (8.0, 12.0), seed=synth.seed_for(2), dtype=np.complex64)
+    z = torch.from_numpy(z_np).cuda()
+
+    results = {}
+    for prec in ("split_bf16", "f32"):
+        ms, stages = run_gpu(z, prec, args.steps, args.warmup)
+        results[prec] = {"ms": ms, "stages": stages}
+
+    pair_samples = N_SIG * (N_SIG - 1) // 2 * T_SAMP
+    main_prec = "split_bf16"
+    ms = results[main_prec]["ms"]
+    line = {
+        "metric": METRIC,
+        "value": round(pair_samples / (ms / 1e3), 1),
+        "unit": "pair-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "sensor-scale analytic PLV: N=1024 complex64 signals x T=60000 samples, "
+                               "lagged oscillators (32 latents, 8-12 Hz), split-BF16 Gram",
+                   "n": N_SIG, "t": T_SAMP, "prec": main_prec},
+        "roofline": roofline(main_prec, N_SIG, T_SAMP, results[main_prec]["stages"]),
+    }
+    stage_ms = {}
+    for prec, r in results.items():
+        stage_ms[prec] = {k: round(v[0] / max(v[1], 1), 4) for k, v in r["stages"].items() if v[1]}
+    line["fp32"] = {"value": round(pair_samples / (results["f32"]["ms"] / 1e3), 1), "ms_per_step":
+                    round(results["f32"]["ms"], 4), "roofline": roofline("f32", N_SIG, T_SAMP,
+                                                                          results["f32"]["stages"])}
+    line["stage_ms"] = stage_ms
+    line["split_vs_fp32_speedup"] = round(results["f32"]["ms"] / ms, 3)
+    if not args.no_cpu:
+        import paper_1710_08037_amd as plv
+        gpu_out = {}
+        for prec in ("split_bf16", "f32"):
+            o = plv.from_analytic(z, prec=prec, want_g=True)
+            torch.cuda.synchronize()
+            gpu_out[prec] = {k: v.cpu().numpy().astype(np.complex128 if k == "g" else np.float64)
+                             for k, v in o.items()}
+        base, errs = cpu_baseline(z_np, gpu_out)
+        line["cpu_baseline"] = base
+        line["max_abs_err_vs_fp64"] = errs
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * plv.h -- C ABI of libplv: Phase Locking Value (PLV), imaginary PLV (iPLV)
+ * and corrected imaginary PLV (ciPLV) of every pair of N signals on one AMD
+ * MI355X (gfx950) GPU.
+ *
+ * Method (Bruna, Maestu, Pereda, "Phase Locking Value revisited"):
+ *   Section II.A, Eq. 4:  each analytic-signal sample is normalised to a unit
+ *                         phasor u = z / |z| (no angle, no exponential);
+ *   Eqs. 5-7:             all pairs at once from one Hermitian product,
+ *                         G = U U^H / T, G_ij = (1/T) sum_t u_i(t) conj(u_j(t));
+ *   Eq. 2 / Eq. 7:        PLV_ij   = |G_ij|;
+ *   Section II.C, Eq. 13: iPLV_ij  = |Im G_ij|;
+ *   Eq. 14:               ciPLV_ij = |Im G_ij| / sqrt(1 - (Re G_ij)^2);
+ *   Eq. 3:                for real input the analytic signal is formed first
+ *                         (DFT-domain one-sided weights, optionally a
+ *                         band-pass brick-wall mask).
+ *
+ * Conventions for every entry point:
+ *   - Pointers inside plv_problem / plv_grad and the workspace are DEVICE
+ *     pointers on the context's device.  Descriptor arrays (plv_problem,
+ *     plv_grad, plv_band) and size outputs are HOST pointers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Compute calls only enqueue work on it and return; results are ready
+ *     when the stream has reached that point.  Descriptor arrays may be freed
+ *     as soon as the call returns.
+ *   - Ownership: the caller allocates and owns every device buffer, including
+ *     the workspace.  Compute entry points never allocate or free device
+ *     memory.  plv_create allocates only host-side state.
+ *   - Errors: arguments are checked on the host before anything is enqueued;
+ *     on PLV_ERR_INVALID_ARG / PLV_ERR_WORKSPACE / PLV_ERR_UNSUPPORTED no
+ *     output is touched.  PLV_ERR_DEVICE means a HIP call or launch failed
+ *     (outputs undefined).  Faults inside kernels surface at the caller's next
+ *     synchronisation.  plv_last_error() gives a message for the last failure
+ *     on a context.  No C++ exception crosses the ABI.
+ *   - Data: NaN/Inf in the input propagate to the affected outputs.  An exact
+ *     zero sample z = 0 is not an error: its phasor is taken as 1 + 0i (the
+ *     phase angle(0) = 0 of the per-pair formulation).
+ *   - Outputs are full symmetric N x N matrices, row-major, with PLV = 1,
+ *     iPLV = 0 and ciPLV = 0 on the diagonal; iPLV and ciPLV are absolute
+ *     values (the signed parts are in G).  ciPLV is 0 where
+ *     (1 - Re G)(1 + Re G) <= 0.
+ *   - The normaliser is 1/T with T the true window length (t1 - t0), never a
+ *     padded length.
+ *   - A context may be used by one host thread at a time.
+ */
+#ifndef PLV_H
+#define PLV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PLV_OK = 0,
+    PLV_ERR_INVALID_ARG = 1, /* a pointer, size, enum or shape is invalid */
+    PLV_ERR_WORKSPACE = 2,   /* workspace NULL, misaligned or smaller than required */
+    PLV_ERR_DEVICE = 3,      /* a HIP runtime call or kernel launch failed */
+    PLV_ERR_UNSUPPORTED = 4  /* a valid request that this build does not implement */
+} plv_status;
+
+/* Arithmetic of the Gram contraction (the phasor planes and the MFMA inputs).
+ * Accumulation is FP32 inside a K-chunk and FP64 across chunks for every mode
+ * except PLV_PREC_F64, which is FP64 throughout. */
+typedef enum {
+    PLV_PREC_F64 = 0,        /* FP64 input, FP64 phasors, FP64 MFMA; f64 / c128 outputs       */
+    PLV_PREC_F32 = 1,        /* FP32 phasors, FP32 MFMA                                        */
+    PLV_PREC_SPLIT_BF16 = 2, /* u = hi + lo in BF16; G ~ hi.hi^H + hi.lo^H + lo.hi^H, BF16 MFMA */
+    PLV_PREC_BF16 = 3,       /* BF16 phasors, BF16 MFMA                                        */
+    PLV_PREC_F16 = 4         /* FP16 phasors, FP16 MFMA                                        */
+} plv_prec;
+
+/* What `in` holds. */
+typedef enum {
+    PLV_INPUT_ANALYTIC = 0, /* interleaved complex analytic signal (c64; c128 for PLV_PREC_F64) */
+    PLV_INPUT_REAL = 1      /* real band-limited signal (f32; f64 for PLV_PREC_F64)              */
+} plv_input;
+
+/* Which entry point a workspace is sized for. */
+typedef enum {
+    PLV_OP_FROM_ANALYTIC = 0,
+    PLV_OP_FROM_REAL = 1,
+    PLV_OP_BACKWARD_ANALYTIC = 2,
+    PLV_OP_BACKWARD_REAL = 3
+} plv_op;
+
+typedef struct plv_ctx plv_ctx;
+
+/* One problem: N signals of one trial.  Several problems (uneven N and T) are
+ * computed by one call, as the Appendix's per-trial loop does one trial at a
+ * time. */
+typedef struct {
+    int64_t n;      /* signals, >= 1                                                  */
+    int64_t t;      /* samples per signal held in `in`, >= 1                          */
+    int64_t ld;     /* row stride of `in` in elements (complex elements for analytic
+                       input), >= t                                                    */
+    int64_t t0, t1; /* samples [t0, t1) enter the Gram, taken AFTER the analytic
+                       signal is formed (trims padding).  t1 = 0 means t1 = t.
+                       Requires 0 <= t0 < t1 <= t.                                     */
+    const void *in; /* [n][ld] signals, device, 8-byte aligned (16 for c128)          */
+    void *plv;      /* [nbands][n][n] outputs, device, or NULL when not wanted:       */
+    void *iplv;     /*   f32 (f64 for PLV_PREC_F64), 4-byte aligned (8 for f64)       */
+    void *ciplv;
+    void *g;        /* [nbands][n][n] complex G = U U^H / T, interleaved (c64, or c128
+                       for PLV_PREC_F64), or NULL.  Needed later by plv_backward.     */
+} plv_problem;
+
+/* Band of the analytic signal for real input, in Hz, both edges included:
+ * weight 2 on the positive-frequency DFT bins k with f_lo <= k*fs/T <= f_hi
+ * (T = the full length t of the row), 0 on every other bin including DC and
+ * Nyquist.  f_lo = f_hi = 0 selects the plain analytic signal (weights 1 at DC,
+ * 2 below Nyquist, 1 at Nyquist for even T, 0 above). */
+typedef struct {
+    double f_lo, f_hi;
+} plv_band;
+
+/* Upstream gradients for plv_backward: dL/d(output) as full [nbands][n][n]
+ * matrices (same dtype as the outputs).  Entry (i,j) and (j,i) both feed pair
+ * {i,j}; the diagonal is ignored.  NULL = zero. */
+typedef struct {
+    const void *dplv, *diplv, *dciplv;
+    void *din; /* output: dL/d(in), same layout, ld and dtype as `in`; for
+                  analytic input dL/dRe z + i dL/dIm z.  Samples outside [t0,t1)
+                  get 0 for analytic input. */
+} plv_grad;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to HIP device `device` (queries its compute-unit
+ * count and kernel occupancy).  device = -1 creates a host-only context that
+ * assumes an MI355X (256 CUs): it can size workspaces and validate arguments,
+ * and compute calls on it return PLV_ERR_INVALID_ARG.  *ctx is NULL on failure. */
+plv_status plv_create(plv_ctx **ctx, int device);
+plv_status plv_destroy(plv_ctx *ctx);
+const char *plv_status_str(plv_status s);
+/* Message for the last failed call on `ctx` ("" if none); valid until the next call. */
+const char *plv_last_error(const plv_ctx *ctx);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t plv_version(void);
+
+/* ---------------------------------------------------------------- timing */
+
+/* Stages of the path, as timed by plv_timing_read. */
+typedef enum {
+    PLV_STAGE_HILBERT = 0,   /* FFT analytic signal (+ normalisation when fused)  */
+    PLV_STAGE_NORMALISE = 1, /* phasor normalisation of analytic input           */
+    PLV_STAGE_GRAM = 2,      /* the Gram contraction on MFMA (all its launches)   */
+    PLV_STAGE_EPILOGUE = 3,  /* chunk sum, metrics and mirrored store             */
+    PLV_STAGE_BACKWARD = 4,  /* adjoint kernels of plv_backward                   */
+    PLV_NSTAGES = 8
+} plv_stage;
+
+typedef struct {
+    double ms[PLV_NSTAGES];       /* summed GPU time per stage, milliseconds */
+    int64_t calls[PLV_NSTAGES];   /* stage executions timed                  */
+    int64_t launches[PLV_NSTAGES];/* kernel launches inside those stages     */
+} plv_timing;
+
+/* Enable (on != 0) or disable per-stage timing on `ctx`.  While enabled each
+ * compute call records a HIP event pair on its stream around every stage
+ * (the host-side cost is a few microseconds per stage). */
+plv_status plv_timing_enable(plv_ctx *ctx, int32_t on);
+/* Wait for the recorded events, add up their times into *out (host) and, if
+ * reset != 0, forget them. */
+plv_status plv_timing_read(plv_ctx *ctx, plv_timing *out, int32_t reset);
+
+/* ------------------------------------------------------------- workspace */
+
+/* Bytes of device workspace a call with these arguments needs (*bytes, host).
+ * The workspace must be 256-byte aligned.  Its contents need no
+ * initialisation and are garbage after the call. */
+plv_status plv_workspace_size(const plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs,
+                              int64_t nprob, const plv_band *bands, int32_t nbands, size_t *bytes);
+
+/* --------------------------------------------------------------- forward */
+
+/* PLV, iPLV, ciPLV (and optionally G) of analytic signals (Eqs. 4-7, 13, 14).
+ * Steps: phasor normalisation -> Gram on MFMA over K-chunks -> fixed-order
+ * chunk sum + metric epilogue with mirrored store.  Outputs are [1][n][n]. */
+plv_status plv_from_analytic(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob, void *ws,
+                             size_t ws_bytes, void *stream);
+
+/* The same from real signals: the analytic signal of every row is formed on
+ * the GPU by FFT for each of the `nbands` bands (Eq. 3), trimmed to [t0, t1),
+ * normalised and contracted.  Outputs are [nbands][n][n].  `bands` may be NULL
+ * with nbands = 1 for the plain analytic signal.  fs > 0 is the sampling rate
+ * in Hz used to place band edges. */
+plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                         const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* -------------------------------------------------------------- backward */
+
+/* Gradient of a scalar loss with respect to the input, given dL/d(outputs).
+ * Not in the paper; the adjoint of the forward map:
+ *   Gbar from the metric derivatives; dL/dU = (Gbar + Gbar^H) U / T on MFMA;
+ *   through u = z/|z|: zbar = i Im(conj(u) ubar) u / |z| (0 at z = 0);
+ *   for real input through the analytic-signal map (a Hermitian operator):
+ *   xbar = Re(IFFT(h .* FFT(zbar))).
+ * Each problem must carry the complex G of the forward call in `g` (same
+ * prec, bands, fs and window); the phasors are recomputed from `in`.
+ * `kind` says what `in` holds; bands/nbands/fs as for plv_from_real (ignored
+ * for analytic input). */
+plv_status plv_backward(plv_ctx *ctx, plv_prec prec, plv_input kind, const plv_problem *probs,
+                        const plv_grad *grads, int64_t nprob, const plv_band *bands, int32_t nbands, double fs,
+                        void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLV_H */

@@ -1,0 +1,168 @@
+"""Torch-facing calls into libplv: allocate outputs and workspace with torch,
+pass raw device pointers and the current HIP stream.  Every step of the
+computation runs in the library's kernels; this module only marshals.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import threading
+
+import torch
+
+from . import _abi
+
+_CTX = {}
+_CTX_LOCK = threading.Lock()
+
+
+class Context:
+    """A libplv context bound to one GPU."""
+
+    def __init__(self, device: int):
+        self.device = device
+        h = C.c_void_p()
+        _abi.check(_abi.lib().plv_create(C.byref(h), int(device)))
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                _abi.lib().plv_destroy(h)
+            except Exception:
+                pass
+
+
+def context(device=None) -> Context:
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    with _CTX_LOCK:
+        if idx not in _CTX:
+            _CTX[idx] = Context(idx)
+        return _CTX[idx]
+
+
+def _prec_id(prec) -> int:
+    if isinstance(prec, int):
+        return prec
+    try:
+        return _abi.PREC[prec]
+    except KeyError:
+        raise ValueError("prec must be one of %s" % sorted(_abi.PREC)) from None
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(dev):
+    return C.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _rows(x: torch.Tensor):
+    if x.dim() != 2:
+        raise ValueError("expected a 2-D [n, t] tensor, got shape %s" % (tuple(x.shape),))
+    if x.stride(1) != 1:
+        raise ValueError("samples must be contiguous (stride 1 along t)")
+    if not x.is_cuda:
+        raise ValueError("input must be a GPU tensor")
+    return x.shape[0], x.shape[1], x.stride(0)
+
+
+def _outputs(n, nb, real_dtype, cplx_dtype, dev, want, want_g):
+    o = {}
+    for k in ("plv", "iplv", "ciplv"):
+        o[k] = torch.empty((nb, n, n), dtype=real_dtype, device=dev) if k in want else None
+    o["g"] = torch.empty((nb, n, n), dtype=cplx_dtype, device=dev) if want_g else None
+    return o
+
+
+def _problem(x, window, outs):
+    n, t, ld = _rows(x)
+    t0, t1 = (0, 0) if window is None else (int(window[0]), int(window[1]))
+    return _abi.Problem(n, t, ld, t0, t1, x.data_ptr(), *(_ptr(outs[k]) for k in ("plv", "iplv", "ciplv", "g")))
+
+
+def _workspace(ctx, op, prec, probs, bands, nb, dev):
+    nbytes = C.c_size_t(0)
+    _abi.check(_abi.lib().plv_workspace_size(ctx.handle, op, prec, probs, len(probs), bands, nb, C.byref(nbytes)),
+               ctx.handle)
+    return torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+
+
+ALL = ("plv", "iplv", "ciplv")
+
+
+def from_analytic_batch(zs, prec="split_bf16", windows=None, want=ALL, want_g=False):
+    """PLV/iPLV/ciPLV of several analytic-signal problems in one grouped call.
+
+    zs: list of complex GPU tensors [n_k, t_k] (complex64; complex128 for f64).
+    Returns a list of dicts with [n_k, n_k] tensors plv, iplv, ciplv and g.
+    """
+    p = _prec_id(prec)
+    dev = zs[0].device
+    cd = torch.complex128 if p == 0 else torch.complex64
+    rd = torch.float64 if p == 0 else torch.float32
+    outs, probs = [], []
+    for k, z in enumerate(zs):
+        if z.dtype != cd:
+            raise TypeError("prec %s needs %s input, got %s" % (prec, cd, z.dtype))
+        o = _outputs(z.shape[0], 1, rd, cd, dev, want, want_g)
+        outs.append(o)
+        probs.append(_problem(z, None if windows is None else windows[k], o))
+    arr = _abi.problems(probs)
+    ctx = context(dev)
+    ws = _workspace(ctx, _abi.OP_FROM_ANALYTIC, p, arr, None, 1, dev)
+    _abi.check(_abi.lib().plv_from_analytic(ctx.handle, p, arr, len(probs), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                            _stream(dev)), ctx.handle)
+    return [{k: (v[0] if v is not None else None) for k, v in o.items()} for o in outs]
+
+
+def from_analytic(z, prec="split_bf16", window=None, want=ALL, want_g=False):
+    """PLV/iPLV/ciPLV of one problem of analytic signals z [n, t]."""
+    return from_analytic_batch([z], prec, None if window is None else [window], want, want_g)[0]
+
+
+def from_real_batch(xs, fs, bands=None, prec="split_bf16", windows=None, want=ALL, want_g=False):
+    """PLV/iPLV/ciPLV of real signals, the analytic signal formed on the GPU.
+
+    xs: list of real GPU tensors [n_k, t_k] (float32; float64 for f64).
+    bands: list of (f_lo, f_hi) in Hz or None for the plain analytic signal.
+    Returns a list of dicts with [nbands, n_k, n_k] tensors.
+    """
+    p = _prec_id(prec)
+    dev = xs[0].device
+    rd = torch.float64 if p == 0 else torch.float32
+    cd = torch.complex128 if p == 0 else torch.complex64
+    barr, nb = _abi.bands(bands)
+    outs, probs = [], []
+    for k, x in enumerate(xs):
+        if x.dtype != rd:
+            raise TypeError("prec %s needs %s input, got %s" % (prec, rd, x.dtype))
+        o = _outputs(x.shape[0], nb, rd, cd, dev, want, want_g)
+        outs.append(o)
+        probs.append(_problem(x, None if windows is None else windows[k], o))
+    arr = _abi.problems(probs)
+    ctx = context(dev)
+    ws = _workspace(ctx, _abi.OP_FROM_REAL, p, arr, barr, nb, dev)
+    _abi.check(_abi.lib().plv_from_real(ctx.handle, p, arr, len(probs), barr, nb, float(fs),
+                                        C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)), ctx.handle)
+    return outs
+
+
+def from_real(x, fs, bands=None, prec="split_bf16", window=None, want=ALL, want_g=False):
+    return from_real_batch([x], fs, bands, prec, None if window is None else [window], want, want_g)[0]
+
+
+def timing_enable(on=True, device=None):
+    """Turn per-stage GPU timing (HIP events on the call's stream) on or off."""
+    ctx = context(device)
+    _abi.check(_abi.lib().plv_timing_enable(ctx.handle, 1 if on else 0), ctx.handle)
+
+
+def timing_read(reset=True, device=None):
+    """{stage: (ms, calls, launches)} summed since the last reset."""
+    ctx = context(device)
+    t = _abi.Timing()
+    _abi.check(_abi.lib().plv_timing_read(ctx.handle, C.byref(t), 1 if reset else 0), ctx.handle)
+    return {name: (t.ms[k], t.calls[k], t.launches[k]) for k, name in enumerate(_abi.STAGES)}

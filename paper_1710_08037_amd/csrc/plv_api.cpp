@@ -1,0 +1,414 @@
+// plv_api.cpp -- the C ABI declared in include/plv.h.
+//
+// Host side only: argument checks, the workspace plan (where each problem's
+// phasor planes, partial sums and the device-side work tables live), the
+// K-chunk choice, and the kernel launches on the caller's stream.  Every step
+// of the computation runs in the gfx950 kernels; nothing here touches data.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "plv_internal.h"
+#include "plv_plan.h"
+
+using namespace plv;
+
+struct TimingRec {
+    int stage;
+    int launches;
+    hipEvent_t start, stop;
+};
+
+struct plv_ctx {
+    int device = -1;
+    int cus = 256;
+    int occ[5] = {1, 1, 1, 1, 1};
+    std::string err;
+    void *staging = nullptr;  // pinned host buffer for the work tables
+    size_t staging_bytes = 0;
+    hipEvent_t staging_done = nullptr;
+    bool staging_pending = false;
+    bool timing = false;
+    std::vector<TimingRec> recs;   // recorded, not yet read
+    std::vector<hipEvent_t> pool;  // idle events
+};
+
+namespace {
+
+plv_status fail(plv_ctx *ctx, plv_status s, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return s;
+}
+
+plv_status hip_fail(plv_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, PLV_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Copy the work tables to the device through the context's pinned buffer.
+plv_status upload(plv_ctx *ctx, const std::vector<uint8_t> &blob, void *dst, hipStream_t s)
+{
+    if (blob.empty())
+        return PLV_OK;
+    hipError_t e;
+    if (ctx->staging_pending) {
+        // the previous call's copy may still be reading the buffer
+        if ((e = hipEventSynchronize(ctx->staging_done)) != hipSuccess)
+            return hip_fail(ctx, e, "hipEventSynchronize");
+        ctx->staging_pending = false;
+    }
+    if (blob.size() > ctx->staging_bytes) {
+        if (ctx->staging)
+            (void)hipHostFree(ctx->staging);
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+        size_t want = std::max<size_t>(blob.size(), size_t(1) << 20);
+        if ((e = hipHostMalloc(&ctx->staging, want, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(ctx, e, "hipHostMalloc");
+        ctx->staging_bytes = want;
+    }
+    memcpy(ctx->staging, blob.data(), blob.size());
+    if ((e = hipMemcpyAsync(dst, ctx->staging, blob.size(), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(ctx, e, "hipMemcpyAsync");
+    if ((e = hipEventRecord(ctx->staging_done, s)) != hipSuccess)
+        return hip_fail(ctx, e, "hipEventRecord");
+    ctx->staging_pending = true;
+    return PLV_OK;
+}
+
+hipEvent_t take_event(plv_ctx *ctx)
+{
+    if (!ctx->pool.empty()) {
+        hipEvent_t e = ctx->pool.back();
+        ctx->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Brackets one stage with an event pair when timing is on.
+struct StageTimer {
+    plv_ctx *ctx;
+    hipStream_t s;
+    TimingRec rec{};
+    bool on = false;
+    StageTimer(plv_ctx *c, int stage, hipStream_t st) : ctx(c), s(st)
+    {
+        if (!ctx->timing)
+            return;
+        rec.stage = stage;
+        rec.start = take_event(ctx);
+        rec.stop = take_event(ctx);
+        on = rec.start && rec.stop && hipEventRecord(rec.start, s) == hipSuccess;
+    }
+    void launched(int k = 1) { rec.launches += k; }
+    ~StageTimer()
+    {
+        if (on && hipEventRecord(rec.stop, s) == hipSuccess)
+            ctx->recs.push_back(rec);
+        else {
+            if (rec.start)
+                ctx->pool.push_back(rec.start);
+            if (rec.stop)
+                ctx->pool.push_back(rec.stop);
+        }
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+plv_status plv_timing_enable(plv_ctx *ctx, int32_t on)
+{
+    if (!ctx)
+        return PLV_ERR_INVALID_ARG;
+    ctx->timing = on != 0 && ctx->device >= 0;
+    return PLV_OK;
+}
+
+plv_status plv_timing_read(plv_ctx *ctx, plv_timing *out, int32_t reset)
+{
+    if (!ctx || !out)
+        return PLV_ERR_INVALID_ARG;
+    memset(out, 0, sizeof *out);
+    for (const TimingRec &r : ctx->recs) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(r.stop);
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, r.start, r.stop);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "reading stage timing events");
+        out->ms[r.stage] += ms;
+        out->calls[r.stage] += 1;
+        out->launches[r.stage] += r.launches;
+    }
+    if (reset) {
+        for (const TimingRec &r : ctx->recs) {
+            ctx->pool.push_back(r.start);
+            ctx->pool.push_back(r.stop);
+        }
+        ctx->recs.clear();
+    }
+    return PLV_OK;
+}
+
+int32_t plv_version(void) { return 10000; }
+
+const char *plv_status_str(plv_status s)
+{
+    switch (s) {
+    case PLV_OK: return "ok";
+    case PLV_ERR_INVALID_ARG: return "invalid argument";
+    case PLV_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case PLV_ERR_DEVICE: return "HIP runtime or launch failure";
+    case PLV_ERR_UNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+const char *plv_last_error(const plv_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+plv_status plv_create(plv_ctx **out, int device)
+{
+    if (!out)
+        return PLV_ERR_INVALID_ARG;
+    *out = nullptr;
+    plv_ctx *ctx = new (std::nothrow) plv_ctx;
+    if (!ctx)
+        return PLV_ERR_DEVICE;
+    if (device >= 0) {
+        int cur = 0, ndev = 0;
+        hipError_t e;
+        if ((e = hipGetDeviceCount(&ndev)) != hipSuccess || device >= ndev) {
+            delete ctx;
+            return e != hipSuccess ? PLV_ERR_DEVICE : PLV_ERR_INVALID_ARG;
+        }
+        (void)hipGetDevice(&cur);
+        if ((e = hipSetDevice(device)) != hipSuccess) {
+            delete ctx;
+            return PLV_ERR_DEVICE;
+        }
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+            ctx->cus = cus;
+        for (int m = 0; m < 5; ++m)
+            ctx->occ[m] = herk_occupancy(m);
+        e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming);
+        (void)hipSetDevice(cur);
+        if (e != hipSuccess) {
+            delete ctx;
+            return PLV_ERR_DEVICE;
+        }
+        ctx->device = device;
+    }
+    *out = ctx;
+    return PLV_OK;
+}
+
+plv_status plv_destroy(plv_ctx *ctx)
+{
+    if (!ctx)
+        return PLV_ERR_INVALID_ARG;
+    if (ctx->staging_pending)
+        (void)hipEventSynchronize(ctx->staging_done);
+    if (ctx->staging)
+        (void)hipHostFree(ctx->staging);
+    if (ctx->staging_done)
+        (void)hipEventDestroy(ctx->staging_done);
+    for (const TimingRec &r : ctx->recs) {
+        (void)hipEventSynchronize(r.stop);
+        ctx->pool.push_back(r.start);
+        ctx->pool.push_back(r.stop);
+    }
+    for (hipEvent_t e : ctx->pool)
+        (void)hipEventDestroy(e);
+    delete ctx;
+    return PLV_OK;
+}
+
+plv_status plv_workspace_size(const plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs,
+                              int64_t nprob, const plv_band *bands, int32_t nbands, size_t *bytes)
+{
+    if (!bytes)
+        return PLV_ERR_INVALID_ARG;
+    *bytes = 0;
+    Plan plan;
+    std::string why;
+    plv_status st = make_plan(ctx ? ctx->cus : 256, ctx ? ctx->occ : nullptr, op, prec, probs, nprob, bands, nbands,
+                              plan, why);
+    if (st != PLV_OK) {
+        if (ctx)
+            const_cast<plv_ctx *>(ctx)->err = why;
+        return st;
+    }
+    *bytes = plan.total;
+    return PLV_OK;
+}
+
+// Shared front half of the compute entry points: checks, plan, device.
+static plv_status begin(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                        const plv_band *bands, int32_t nbands, void *ws, size_t ws_bytes, Plan &plan)
+{
+    if (!ctx)
+        return PLV_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (ctx->device < 0)
+        return fail(ctx, PLV_ERR_INVALID_ARG, "host-only context cannot compute");
+    std::string why;
+    plv_status st = make_plan(ctx->cus, ctx->occ, op, prec, probs, nprob, bands, nbands, plan, why);
+    if (st != PLV_OK)
+        return fail(ctx, st, "%s", why.c_str());
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
+        return fail(ctx, PLV_ERR_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < plan.total)
+        return fail(ctx, PLV_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, plan.total);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "hipSetDevice");
+    return PLV_OK;
+}
+
+// Gram + epilogue over every Gram problem of the plan (phasors already in ws).
+static plv_status run_gram(plv_ctx *ctx, const Plan &plan, uint8_t *ws, hipStream_t s)
+{
+    const int mode = plan.mode;
+    std::vector<GramDesc> gd;
+    fill_descs(plan, ws, gd);
+    hipError_t e;
+    if (gd.size() == 1) {
+        const GramDesc &d = gd[0];
+        const int passes = (d.nchunk + d.nslot - 1) / d.nslot;
+        {
+            StageTimer tm(ctx, PLV_STAGE_GRAM, s);
+            for (int p = 0; p < passes; ++p) {
+                HerkArgs ha{};
+                ha.g = d;
+                ha.pass = p;
+                const int nch = std::min(d.nslot, d.nchunk - p * d.nslot);
+                if ((e = launch_herk(mode, ha, d.nupper * nch, s)) != hipSuccess)
+                    return hip_fail(ctx, e, "gram kernel launch");
+                tm.launched();
+            }
+        }
+        StageTimer tm(ctx, PLV_STAGE_EPILOGUE, s);
+        EpiArgs ea{};
+        ea.g = gd[0];
+        if ((e = launch_epilogue(mode, ea, gd[0].nupper, s)) != hipSuccess)
+            return hip_fail(ctx, e, "epilogue kernel launch");
+        tm.launched();
+        return PLV_OK;
+    }
+    std::vector<uint8_t> blob;
+    std::vector<Item> items;
+    std::vector<TileRef> tiles;
+    build_tables(plan, gd, items, tiles);
+    blob.resize(plan.tables_bytes, 0);
+    memcpy(blob.data() + plan.desc_off - plan.tables_off, gd.data(), gd.size() * sizeof(GramDesc));
+    memcpy(blob.data() + plan.item_off - plan.tables_off, items.data(), items.size() * sizeof(Item));
+    memcpy(blob.data() + plan.tile_off - plan.tables_off, tiles.data(), tiles.size() * sizeof(TileRef));
+    plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
+    if (st != PLV_OK)
+        return st;
+    HerkArgs ha{};
+    ha.gd = (const GramDesc *)(ws + plan.desc_off);
+    ha.items = (const Item *)(ws + plan.item_off);
+    ha.nitems = (int32_t)items.size();
+    {
+        StageTimer tm(ctx, PLV_STAGE_GRAM, s);
+        if ((e = launch_herk(mode, ha, (int)items.size(), s)) != hipSuccess)
+            return hip_fail(ctx, e, "gram kernel launch");
+        tm.launched();
+    }
+    StageTimer tm(ctx, PLV_STAGE_EPILOGUE, s);
+    EpiArgs ea{};
+    ea.gd = ha.gd;
+    ea.tiles = (const TileRef *)(ws + plan.tile_off);
+    if ((e = launch_epilogue(mode, ea, (int)tiles.size(), s)) != hipSuccess)
+        return hip_fail(ctx, e, "epilogue kernel launch");
+    tm.launched();
+    return PLV_OK;
+}
+
+plv_status plv_from_analytic(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob, void *ws,
+                             size_t ws_bytes, void *stream)
+{
+    Plan plan;
+    plv_status st = begin(ctx, PLV_OP_FROM_ANALYTIC, prec, probs, nprob, nullptr, 1, ws, ws_bytes, plan);
+    if (st != PLV_OK)
+        return st;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t *w = (uint8_t *)ws;
+    {
+    StageTimer tm(ctx, PLV_STAGE_NORMALISE, s);
+    for (const GramPlan &gp : plan.grams) {
+        const plv_problem &p = probs[gp.prob];
+        NormArgs na{};
+        na.in = p.in;
+        na.ld = p.ld;
+        na.t0 = gp.t0;
+        na.tw = gp.t;
+        na.n = gp.n;
+        na.u = w + gp.u_off;
+        na.plane_bytes = (int64_t)gp.plane_bytes;
+        na.ldu = gp.tpad;
+        na.tpad = gp.tpad;
+        hipError_t e = launch_normalise(plan.mode, na, s);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "normalise kernel launch");
+        tm.launched();
+    }
+    }
+    return run_gram(ctx, plan, w, s);
+}
+
+plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                         const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes, void *stream)
+{
+    (void)fs;
+    Plan plan;
+    plv_status st = begin(ctx, PLV_OP_FROM_REAL, prec, probs, nprob, bands, nbands, ws, ws_bytes, plan);
+    if (st != PLV_OK)
+        return st;
+    (void)stream;
+    return fail(ctx, PLV_ERR_UNSUPPORTED, "plv_from_real: not built yet");
+}
+
+plv_status plv_backward(plv_ctx *ctx, plv_prec prec, plv_input kind, const plv_problem *probs,
+                        const plv_grad *grads, int64_t nprob, const plv_band *bands, int32_t nbands, double fs,
+                        void *ws, size_t ws_bytes, void *stream)
+{
+    (void)prec;
+    (void)kind;
+    (void)probs;
+    (void)grads;
+    (void)nprob;
+    (void)bands;
+    (void)nbands;
+    (void)fs;
+    (void)ws;
+    (void)ws_bytes;
+    (void)stream;
+    if (!ctx)
+        return PLV_ERR_INVALID_ARG;
+    return fail(ctx, PLV_ERR_UNSUPPORTED, "plv_backward: not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,239 @@
+// plv_plan.cpp -- argument checks, workspace layout and K-chunk choice.
+#include "plv_plan.h"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace plv {
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+std::string msg(const char *fmt, long long a = 0, long long b = 0)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, fmt, a, b);
+    return buf;
+}
+
+// K-chunks of a problem computed alone: enough (tile, chunk) items to fill
+// every work-group slot once, no chunk longer than MAX_CHUNK, none shorter
+// than MIN_CHUNK unless T itself is.  Partial slots are capped by
+// PARTIAL_BUDGET; beyond it the chunks run in passes.
+void choose_chunks_single(GramPlan &g, int slots, int bm)
+{
+    const int kgr = g.tpad / PLV_KGRAN;
+    int nc = 1;
+    if (g.nupper < slots)
+        nc = std::max(1, std::min(kgr, slots / g.nupper));
+    if (nc > 1 && g.tpad / nc < MIN_CHUNK)
+        nc = std::max(1, g.tpad / MIN_CHUNK);
+    nc = std::max(nc, (g.tpad + MAX_CHUNK - 1) / MAX_CHUNK);
+    const int per = (kgr + nc - 1) / nc;  // granules per chunk
+    g.chunk = per * PLV_KGRAN;
+    g.nchunk = (kgr + per - 1) / per;
+    const size_t slot_bytes = (size_t)g.nupper * 2 * bm * bm * sizeof(double);
+    g.nslot = (int)std::max<size_t>(1, std::min<size_t>(g.nchunk, PARTIAL_BUDGET / slot_bytes));
+}
+
+// Inside a grouped launch every chunk of a problem has its own slot (one pass).
+void choose_chunks_grouped(GramPlan &g)
+{
+    const int kgr = g.tpad / PLV_KGRAN;
+    const int per = std::min(kgr, MAX_CHUNK / PLV_KGRAN);
+    g.chunk = per * PLV_KGRAN;
+    g.nchunk = (kgr + per - 1) / per;
+    g.nslot = g.nchunk;
+}
+
+}  // namespace
+
+plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why)
+{
+    plan = Plan();
+    if ((int)prec < 0 || (int)prec > 4) {
+        why = "unknown precision";
+        return PLV_ERR_INVALID_ARG;
+    }
+    if ((int)op < 0 || (int)op > 3) {
+        why = "unknown op";
+        return PLV_ERR_INVALID_ARG;
+    }
+    if (!probs || nprob < 1 || nprob > (1 << 24)) {
+        why = msg("need 1 <= nprob <= 2^24 problems and a non-NULL array (nprob = %lld)", (long long)nprob);
+        return PLV_ERR_INVALID_ARG;
+    }
+    const bool real = (op == PLV_OP_FROM_REAL || op == PLV_OP_BACKWARD_REAL);
+    if (real) {
+        if (nbands < 1 || nbands > 64) {
+            why = msg("need 1 <= nbands <= 64 (nbands = %lld)", nbands);
+            return PLV_ERR_INVALID_ARG;
+        }
+        if (bands) {
+            for (int b = 0; b < nbands; ++b)
+                if (!(bands[b].f_lo >= 0.0) || !(bands[b].f_hi >= bands[b].f_lo)) {
+                    why = msg("band %lld: need 0 <= f_lo <= f_hi", b);
+                    return PLV_ERR_INVALID_ARG;
+                }
+        } else if (nbands != 1) {
+            why = "bands == NULL requires nbands == 1";
+            return PLV_ERR_INVALID_ARG;
+        }
+    } else {
+        nbands = 1;
+    }
+    const int mode = (int)prec;
+    plan.mode = mode;
+    plan.op = op;
+    const int bm = tile_of(mode);
+    const int cb = cbytes_of(mode);
+    const int pl = planes_of(mode);
+    const size_t in_elem = (mode == M_F64 ? 8 : 4) * (real ? 1 : 2);
+    const size_t out_elem = (mode == M_F64 ? 8 : 4);
+
+    for (int64_t q = 0; q < nprob; ++q) {
+        const plv_problem &p = probs[q];
+        const int64_t t1 = p.t1 == 0 ? p.t : p.t1;
+        if (p.n < 1 || p.n > (1 << 20)) {
+            why = msg("problem %lld: need 1 <= n <= 2^20 (n = %lld)", q, p.n);
+            return PLV_ERR_INVALID_ARG;
+        }
+        if (p.t < 1 || p.t > (int64_t(1) << 30)) {
+            why = msg("problem %lld: need 1 <= t <= 2^30 (t = %lld)", q, p.t);
+            return PLV_ERR_INVALID_ARG;
+        }
+        if (p.ld < p.t) {
+            why = msg("problem %lld: need ld >= t (ld = %lld)", q, p.ld);
+            return PLV_ERR_INVALID_ARG;
+        }
+        if (p.t0 < 0 || t1 <= p.t0 || t1 > p.t) {
+            why = msg("problem %lld: need 0 <= t0 < t1 <= t (t0 = %lld)", q, p.t0);
+            return PLV_ERR_INVALID_ARG;
+        }
+        if (!p.in) {
+            why = msg("problem %lld: input is NULL", q);
+            return PLV_ERR_INVALID_ARG;
+        }
+        const size_t in_align = std::min<size_t>(in_elem, 16);
+        if (reinterpret_cast<uintptr_t>(p.in) % in_align) {
+            why = msg("problem %lld: input must be %lld-byte aligned", q, (long long)in_align);
+            return PLV_ERR_INVALID_ARG;
+        }
+        const void *outs[4] = {p.plv, p.iplv, p.ciplv, p.g};
+        for (int k = 0; k < 4; ++k)
+            if (outs[k] && reinterpret_cast<uintptr_t>(outs[k]) % out_elem) {
+                why = msg("problem %lld: outputs must be %lld-byte aligned", q, (long long)out_elem);
+                return PLV_ERR_INVALID_ARG;
+            }
+        if ((op == PLV_OP_BACKWARD_ANALYTIC || op == PLV_OP_BACKWARD_REAL) && !p.g) {
+            why = msg("problem %lld: backward needs the forward's complex G in `g`", q);
+            return PLV_ERR_INVALID_ARG;
+        }
+        for (int b = 0; b < nbands; ++b) {
+            GramPlan g;
+            g.prob = q;
+            g.band = b;
+            g.n = (int)p.n;
+            g.npad = (int)((p.n + bm - 1) / bm * bm);
+            g.t0 = (int)p.t0;
+            g.t = (int)(t1 - p.t0);
+            g.tpad = (g.t + PLV_KGRAN - 1) / PLV_KGRAN * PLV_KGRAN;
+            g.ntile = g.npad / bm;
+            g.nupper = g.ntile * (g.ntile + 1) / 2;
+            const size_t nn = (size_t)p.n * (size_t)p.n;
+            const size_t ob = (size_t)b * nn * out_elem;
+            g.plv = p.plv ? (uint8_t *)p.plv + ob : nullptr;
+            g.iplv = p.iplv ? (uint8_t *)p.iplv + ob : nullptr;
+            g.ciplv = p.ciplv ? (uint8_t *)p.ciplv + ob : nullptr;
+            g.g = p.g ? (uint8_t *)p.g + 2 * ob : nullptr;
+            plan.grams.push_back(g);
+        }
+    }
+
+    const int slots = std::max(1, cus) * std::max(1, occ ? occ[mode] : 1);
+    const bool grouped = plan.grams.size() > 1;
+    size_t off = 0;
+    if (grouped) {
+        for (GramPlan &g : plan.grams)
+            choose_chunks_grouped(g);
+        for (const GramPlan &g : plan.grams) {
+            plan.nitems += (size_t)g.nupper * g.nchunk;
+            plan.ntiles += (size_t)g.nupper;
+        }
+        if (plan.nitems > (size_t)INT32_MAX || plan.ntiles > (size_t)INT32_MAX) {
+            why = "too many work items";
+            return PLV_ERR_INVALID_ARG;
+        }
+        plan.tables_off = 0;
+        plan.desc_off = 0;
+        plan.item_off = align256(plan.grams.size() * sizeof(GramDesc));
+        plan.tile_off = plan.item_off + align256(plan.nitems * sizeof(Item));
+        plan.tables_bytes = plan.tile_off + align256(plan.ntiles * sizeof(TileRef));
+        off = plan.tables_bytes;
+    } else {
+        choose_chunks_single(plan.grams[0], slots, bm);
+    }
+    for (GramPlan &g : plan.grams) {
+        g.plane_bytes = align256((size_t)g.npad * g.tpad * cb);
+        g.u_off = off;
+        off += g.plane_bytes * pl;
+    }
+    for (GramPlan &g : plan.grams) {
+        g.part_off = off;
+        off += align256((size_t)g.nslot * g.nupper * 2 * bm * bm * sizeof(double));
+    }
+    plan.total = off;
+    return PLV_OK;
+}
+
+void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd)
+{
+    gd.clear();
+    for (const GramPlan &g : plan.grams) {
+        GramDesc d{};
+        d.u = ws + g.u_off;
+        d.plane_bytes = (int64_t)g.plane_bytes;
+        d.ldu = g.tpad;
+        d.n = g.n;
+        d.npad = g.npad;
+        d.t = g.t;
+        d.tpad = g.tpad;
+        d.ntile = g.ntile;
+        d.nupper = g.nupper;
+        d.nchunk = g.nchunk;
+        d.chunk = g.chunk;
+        d.nslot = g.nslot;
+        d.partial = (double *)(ws + g.part_off);
+        d.plv = g.plv;
+        d.iplv = g.iplv;
+        d.ciplv = g.ciplv;
+        d.g = g.g;
+        gd.push_back(d);
+    }
+}
+
+void build_tables(const Plan &plan, const std::vector<GramDesc> &gd, std::vector<Item> &items,
+                  std::vector<TileRef> &tiles)
+{
+    items.clear();
+    tiles.clear();
+    items.reserve(plan.nitems);
+    tiles.reserve(plan.ntiles);
+    for (size_t q = 0; q < gd.size(); ++q) {
+        const GramDesc &d = gd[q];
+        for (int c = 0; c < d.nchunk; ++c)
+            for (int t = 0; t < d.nupper; ++t)
+                items.push_back(Item{(int32_t)q, t, c, 0});
+        for (int t = 0; t < d.nupper; ++t)
+            tiles.push_back(TileRef{(int32_t)q, t});
+    }
+    // longest items first, so the tail of the launch is short work
+    auto cost = [&](const Item &it) {
+        const GramDesc &d = gd[it.gram];
+        return std::min(d.chunk, d.tpad - it.chunk * d.chunk);
+    };
+    std::stable_sort(items.begin(), items.end(), [&](const Item &a, const Item &b) { return cost(a) > cost(b); });
+}
+
+}  // namespace plv

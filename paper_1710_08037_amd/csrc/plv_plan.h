@@ -1,0 +1,49 @@
+// plv_plan.h -- host-side planning: argument checks, workspace layout, K-chunks.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "plv_internal.h"
+
+namespace plv {
+
+constexpr int MAX_CHUNK = 8192;      // longest FP32 accumulation span of one work item (samples)
+constexpr int MIN_CHUNK = 1024;      // shortest K-chunk worth a work-group
+constexpr size_t PARTIAL_BUDGET = size_t(2) << 30;  // partial-slot bytes before T is split into passes
+
+struct GramPlan {
+    int64_t prob = 0;
+    int band = 0;
+    int n = 0, npad = 0;
+    int t = 0, t0 = 0, tpad = 0;       // window length, window start, padded length
+    int ntile = 0, nupper = 0;
+    int nchunk = 0, chunk = 0, nslot = 0;
+    size_t u_off = 0, plane_bytes = 0; // phasor planes
+    size_t part_off = 0;               // FP64 partial sums
+    void *plv = nullptr, *iplv = nullptr, *ciplv = nullptr, *g = nullptr;
+};
+
+struct Plan {
+    int mode = 0;
+    plv_op op = PLV_OP_FROM_ANALYTIC;
+    std::vector<GramPlan> grams;
+    size_t tables_off = 0, tables_bytes = 0;  // device work tables (grouped launch only)
+    size_t desc_off = 0, item_off = 0, tile_off = 0;
+    size_t nitems = 0, ntiles = 0;
+    size_t total = 0;
+};
+
+// Checks the arguments and lays out the workspace.  `occ` (work-groups per CU
+// of the Gram kernel, per mode) may be NULL: then 1 is assumed.
+plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why);
+
+void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd);
+void build_tables(const Plan &plan, const std::vector<GramDesc> &gd, std::vector<Item> &items,
+                  std::vector<TileRef> &tiles);
+
+}  // namespace plv
