@@ -119,6 +119,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--prec", default="both", choices=["both", "split_bf16", "f32"],
+                    help="paths to time (both: split-BF16 for `value`, FP32 beside it)")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes 3 times (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X (use --gpus 1)", file=sys.stderr)
@@ -130,13 +134,25 @@ def main():
     import synth
 
     torch.cuda.set_device(0)
+    if args.copy_ref:
+        src = torch.empty(args.copy_ref, dtype=torch.uint8, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes": args.copy_ref}), flush=True)
+        return
     z_np = synth.glag_analytic(N_SIG, T_SAMP, FS, 32, (8.0, 12.0), seed=synth.seed_for(2), dtype=np.complex64)
     z = torch.from_numpy(z_np).cuda()
 
     results = {}
-    for prec in ("split_bf16", "f32"):
+    precs = ("split_bf16", "f32") if args.prec == "both" else (args.prec,)
+    for prec in precs:
         ms, stages = run_gpu(z, prec, args.steps, args.warmup)
         results[prec] = {"ms": ms, "stages": stages}
+    if args.prec == "f32":
+        print(json.dumps({"f32_ms_per_step": results["f32"]["ms"]}), flush=True)
+        return
 
     pair_samples = N_SIG * (N_SIG - 1) // 2 * T_SAMP
     main_prec = "split_bf16"
@@ -162,15 +178,16 @@ def main():
     stage_ms = {}
     for prec, r in results.items():
         stage_ms[prec] = {k: round(v[0] / max(v[1], 1), 4) for k, v in r["stages"].items() if v[1]}
-    line["fp32"] = {"value": round(pair_samples / (results["f32"]["ms"] / 1e3), 1), "ms_per_step":
-                    round(results["f32"]["ms"], 4), "roofline": roofline("f32", N_SIG, T_SAMP,
-                                                                          results["f32"]["stages"])}
+    if "f32" in results:
+        line["fp32"] = {"value": round(pair_samples / (results["f32"]["ms"] / 1e3), 1), "ms_per_step":
+                        round(results["f32"]["ms"], 4), "roofline": roofline("f32", N_SIG, T_SAMP,
+                                                                              results["f32"]["stages"])}
+        line["split_vs_fp32_speedup"] = round(results["f32"]["ms"] / ms, 3)
     line["stage_ms"] = stage_ms
-    line["split_vs_fp32_speedup"] = round(results["f32"]["ms"] / ms, 3)
     if not args.no_cpu:
         import paper_1710_08037_amd as plv
         gpu_out = {}
-        for prec in ("split_bf16", "f32"):
+        for prec in precs:
             o = plv.from_analytic(z, prec=prec, want_g=True)
             torch.cuda.synchronize()
             gpu_out[prec] = {k: v.cpu().numpy().astype(np.complex128 if k == "g" else np.float64)

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
 {
     constexpr int BM = tile_of(MODE);
     typedef typename std::conditional<MODE == M_F64, double, float>::type real_t;
-    typedef typename std::conditional<MODE == M_F64, double2, float2>::type cplx_t;
+    typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
 
     GramDesc d;
     int tile;
@@ -42,12 +42,12 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
     }
     const int J = I + (tile - base);
 
-    const double *part = d.partial + (int64_t)tile * 2 * BM * BM;
+    auto part = gptr((const double *)d.partial + (int64_t)tile * 2 * BM * BM);
     const int64_t cstride = (int64_t)d.nupper * 2 * BM * BM;
     const double inv_t = 1.0 / (double)d.t;
     const int64_t n = d.n;
-    real_t *plv = (real_t *)d.plv, *iplv = (real_t *)d.iplv, *ciplv = (real_t *)d.ciplv;
-    cplx_t *g = (cplx_t *)d.g;
+    auto plv = gptr((real_t *)d.plv), iplv = gptr((real_t *)d.iplv), ciplv = gptr((real_t *)d.ciplv);
+    auto g = gptr((cplx_t *)d.g);
 
 #pragma unroll
     for (int k = 0; k < 4; ++k) {

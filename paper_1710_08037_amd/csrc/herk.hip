@@ -20,11 +20,11 @@
 // lanes separately (4 samples per instruction, 4 products).
 //
 // Tiling (all modes): 256 threads = 4 waves in 2 x 2, each wave a
-// (BM/2) x (BM/2) sub-tile made of 16 x 16 MFMA blocks.  Each K-stage stages
-// 128 bytes per row (32 / 16 / 8 samples for 16-bit / f32 / f64) of the row
-// panel I and the column panel J into LDS (row pitch 144 B: the 16 B pad makes
-// the 16-lane fragment reads conflict-free), double-buffered with one barrier
-// per stage and the next stage's global loads in flight during the MFMAs.
+// (BM/2) x (BM/2) sub-tile made of 16 x 16 MFMA blocks.  Each K-stage holds
+// 64 bytes per row (16 / 8 / 4 samples for 16-bit / f32 / f64) of the row
+// panel I and the column panel J.  They move global -> LDS directly
+// (global_load_lds_dwordx4, no staging registers) into a ring of NS stages,
+// with the 16-byte positions of each 64-byte LDS row XOR-swizzled by row.
 // A diagonal tile (I == J) loads one panel and uses it as both operands.
 //
 // Work-groups are handed out XCD-aware: the hardware deals work-group ids
@@ -42,18 +42,26 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int ROWB = 128;  // bytes per row per K-stage
-constexpr int LROW = 144;  // LDS row pitch
+constexpr int RB = 64;  // bytes of one row staged per K-stage, per plane
+
+// LDS ring depth per mode: (NS - 1) stages of loads are in flight while one
+// is consumed.  Stage bytes = planes x 2 panels x BM rows x 64 B.
+template <int MODE>
+struct Ring {
+    static constexpr int BM = tile_of(MODE);
+    static constexpr int PL = planes_of(MODE);
+    static constexpr int PANEL = BM * RB;          // one panel of one plane
+    static constexpr int STAGE = PL * 2 * PANEL;   // A and B panels of every plane
+    static constexpr int NS = (MODE == M_SPLIT) ? 4 : 8;
+};
 
 template <int MODE>
 struct AccOf {
     typedef f32x4 type;
-    typedef float scalar;
 };
 template <>
 struct AccOf<M_F64> {
     typedef f64x4 type;
-    typedef double scalar;
 };
 
 __device__ inline int xcd_remap(int wg, int nwg)
@@ -76,6 +84,14 @@ __device__ inline void tile_ij(int tile, int nt, int &I, int &J)
     J = i + (tile - base);
 }
 
+// LDS layout of one stage: each panel is a run of 1 KB blocks of 16 rows x
+// 64 bytes, row-major, with the four 16-byte positions of each row
+// XOR-swizzled by the row's index in its block.  The direct loads stay
+// coalesced (four lanes fetch one row's 64 contiguous bytes) and the MFMA
+// fragment reads (lane l: row l % 16, segment l / 16) spread over the banks.
+// Measured on gfx950 this beats both plain 64-byte rows (FP32 fragments
+// conflict) and a segment-major block (its loads coalesce poorly).
+__device__ inline int swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
 // (re, im) -> (im, -re) for each packed 16-bit pair.
 __device__ inline u32x4 swap_neg(u32x4 v)
 {
@@ -97,20 +113,231 @@ __device__ inline f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c)
                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// s_waitcnt on the vector-memory counter only (gfx9 encoding: vmcnt in bits
+// 3:0 and 15:14, expcnt and lgkmcnt left at their maxima).
+template <int N>
+__device__ inline void wait_vm()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+// Work-group barrier without a memory fence.  __syncthreads() would make
+// every wave drain all of its in-flight loads first (vmcnt(0)), which would
+// collapse the ring to one stage; each wave instead waits for its own loads
+// of the stage about to be read (wait_vm) and then meets the others here.
+// The empty asm keeps the compiler from moving LDS accesses across it.
+__device__ inline void stage_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef const __attribute__((address_space(1))) void gvoid;
+
+constexpr int WAVES = 8;   // two groups of four waves per work-group
+constexpr int THREADS = 64 * WAVES;
+
+template <int MODE, bool DIAG>
+__device__ inline void herk_tile(const GramDesc &d, int I, int J, int k0, int nst,
+                                 typename AccOf<MODE>::type (&re)[tile_of(MODE) / 32][tile_of(MODE) / 32],
+                                 typename AccOf<MODE>::type (&im)[tile_of(MODE) / 32][tile_of(MODE) / 32],
+                                 uint8_t *smem)
+{
+    typedef Ring<MODE> R;
+    constexpr int BM = R::BM, NB = BM / 32, PL = R::PL, PANEL = R::PANEL, STAGE = R::STAGE, NS = R::NS;
+    constexpr int NR = NS / 2;                    // rounds held by the ring (2 stages per round)
+    constexpr int CB = cbytes_of(MODE);
+    constexpr int BLKS = PANEL / 1024;            // 1 KB load blocks per panel and plane
+    constexpr int SLOTS = PL * (DIAG ? 1 : 2) * BLKS;  // load blocks per stage
+    static_assert(SLOTS % WAVES == 0 || SLOTS < WAVES, "load blocks per wave");
+    constexpr int LPS = (SLOTS + WAVES - 1) / WAVES;    // loads per stage per wave (last ones may idle)
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int grp = wave >> 2, wq = wave & 3;
+    const int wm = wq >> 1, wn = wq & 1;
+
+    // ---- direct global -> LDS loads: lane L of a 1 KB block stages row L/4,
+    // LDS position L%4, which holds the row's segment (L%4) ^ swz(L/4).
+    const int64_t pitch = d.ldu * CB;
+    const int lr = lane >> 2;
+    const uint32_t voff = (uint32_t)(lr * pitch) + (uint32_t)(((lane & 3) ^ swz(lr)) * 16);
+    const uint8_t *gA = d.u + (int64_t)I * BM * pitch + (int64_t)k0 * CB;
+    const uint8_t *gB = d.u + (int64_t)J * BM * pitch + (int64_t)k0 * CB;
+    auto issue = [&](int st, int buf) {
+        const int64_t koff = (int64_t)st * RB;
+        uint8_t *base = smem + buf * STAGE;
+#pragma unroll
+        for (int q = 0; q < LPS; ++q) {
+            const int slot = wave + WAVES * q;   // wave-uniform
+            if (slot < SLOTS) {
+                const int blk = slot % BLKS;
+                const int pp = slot / BLKS;      // plane * (1 or 2) + panel
+                const int p = DIAG ? pp : (pp >> 1);
+                const int isb = DIAG ? 0 : (pp & 1);
+                const uint8_t *g = (isb ? gB : gA) + p * d.plane_bytes + (int64_t)blk * 16 * pitch + koff;
+                __builtin_amdgcn_global_load_lds((gvoid *)(g + voff),
+                                                 (lds_void *)(base + p * 2 * PANEL + isb * PANEL + blk * 1024),
+                                                 16, 0, 0);
+            }
+        }
+    };
+
+    // ---- fragment addressing (row within a 16-row block = lane & 15)
+    const int fr = lane & 15;
+    const int arow = (wm * (BM / 2) + fr) * RB;
+    const int brow = (wn * (BM / 2) + fr) * RB + (DIAG ? 0 : PANEL);
+
+    auto compute = [&](int buf) {
+        const uint8_t *S = smem + buf * STAGE;
+        if constexpr (CB == 4) {
+            // 16 samples = one K' = 32 step of v_mfma_*_16x16x32
+            const int off = (((lane >> 4) ^ swz(fr)) * 16);
+            u32x4 vb[PL][NB];
+#pragma unroll
+            for (int p = 0; p < PL; ++p)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    vb[p][b] = *(const u32x4 *)(S + p * 2 * PANEL + brow + b * 16 * RB + off);
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                u32x4 va[PL], vq[PL];
+#pragma unroll
+                for (int p = 0; p < PL; ++p) {
+                    va[p] = *(const u32x4 *)(S + p * 2 * PANEL + arow + a * 16 * RB + off);
+                    vq[p] = swap_neg(va[p]);
+                }
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    re[a][b] = mfma16<MODE>(va[0], vb[0][b], re[a][b]);
+                    im[a][b] = mfma16<MODE>(vq[0], vb[0][b], im[a][b]);
+                    if constexpr (PL == 2) {
+                        re[a][b] = mfma16<MODE>(va[0], vb[1][b], re[a][b]);
+                        im[a][b] = mfma16<MODE>(vq[0], vb[1][b], im[a][b]);
+                        re[a][b] = mfma16<MODE>(va[1], vb[0][b], re[a][b]);
+                        im[a][b] = mfma16<MODE>(vq[1], vb[0][b], im[a][b]);
+                    }
+                }
+            }
+        } else if constexpr (CB == 8) {
+            // FP32: 8 samples = 2 steps of 4; one sample (re, im) per lane
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int off = (((ks * 2 + (lane >> 5)) ^ swz(fr)) * 16) + ((lane >> 4) & 1) * 8;
+                float2 vb[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    vb[b] = *(const float2 *)(S + brow + b * 16 * RB + off);
+#pragma unroll
+                for (int a = 0; a < NB; ++a) {
+                    const float2 va = *(const float2 *)(S + arow + a * 16 * RB + off);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb[b].x, re[a][b], 0, 0, 0);
+                        re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb[b].y, re[a][b], 0, 0, 0);
+                        im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb[b].x, im[a][b], 0, 0, 0);
+                        im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-va.x, vb[b].y, im[a][b], 0, 0, 0);
+                    }
+                }
+            }
+        } else {
+            // FP64: 4 samples = 1 step of 4; one sample (re, im) per lane
+            const int off = (((lane >> 4) ^ swz(fr)) * 16);
+            double2 vb[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                vb[b] = *(const double2 *)(S + brow + b * 16 * RB + off);
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                const double2 va = *(const double2 *)(S + arow + a * 16 * RB + off);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.x, vb[b].x, re[a][b], 0, 0, 0);
+                    re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, vb[b].y, re[a][b], 0, 0, 0);
+                    im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, vb[b].x, im[a][b], 0, 0, 0);
+                    im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-va.x, vb[b].y, im[a][b], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    // ---- K loop.  Stages go in rounds of two: group 0 takes the even stage,
+    // group 1 the odd one, so two waves share each SIMD.  The ring holds NR
+    // rounds; each round: wait for this round's own loads, one barrier
+    // (everyone's loads landed, everyone is done with the previous round's
+    // buffers), refill those buffers NR - 1 rounds ahead, compute.
+    const int nround = (nst + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < NS - 2; ++i)
+        if (i < nst)
+            issue(i, i);
+    for (int r = 0; r < nround; ++r) {
+        // Loads issued after this round's: rounds r+1 .. r+NR-2, LPS per
+        // stage per wave (each wave issues exactly LPS or none).  Waiting down
+        // to that many is exact only when all of those stages exist;
+        // otherwise wait for everything.
+        if (NR > 2 && 2 * (r + NR - 2) + 1 < nst)
+            wait_vm<(NS - 4) * LPS>();
+        else
+            wait_vm<0>();
+        stage_barrier();
+        const int nxt = r + NR - 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (2 * nxt + h < nst)
+                issue(2 * nxt + h, (2 * nxt + h) % NS);
+        const int st = 2 * r + grp;
+        if (st < nst)
+            compute(st % NS);
+    }
+}
+
+// Folds group 1's accumulators into group 0's through LDS (after the K loop).
 template <int MODE>
-__global__ __launch_bounds__(256) void herk_kernel(HerkArgs args)
+__device__ inline void fold_groups(typename AccOf<MODE>::type (&re)[tile_of(MODE) / 32][tile_of(MODE) / 32],
+                                   typename AccOf<MODE>::type (&im)[tile_of(MODE) / 32][tile_of(MODE) / 32],
+                                   uint8_t *smem)
+{
+    constexpr int NB = tile_of(MODE) / 32;
+    typedef typename AccOf<MODE>::type acc_t;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int grp = wave >> 2, wq = wave & 3;
+    acc_t *buf = (acc_t *)smem + (size_t)wq * NB * NB * 2 * 64;
+    __syncthreads();  // every wave is done reading the ring
+    if (grp == 1) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                buf[((a * NB + b) * 2 + 0) * 64 + lane] = re[a][b];
+                buf[((a * NB + b) * 2 + 1) * 64 + lane] = im[a][b];
+            }
+    }
+    __syncthreads();
+    if (grp == 0) {
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                re[a][b] += buf[((a * NB + b) * 2 + 0) * 64 + lane];
+                im[a][b] += buf[((a * NB + b) * 2 + 1) * 64 + lane];
+            }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
 {
     constexpr int BM = tile_of(MODE);
-    constexpr int NB = BM / 32;            // 16x16 blocks per wave side
-    constexpr int CB = cbytes_of(MODE);
-    constexpr int PL = planes_of(MODE);
-    constexpr int BKC = ROWB / CB;         // samples per K-stage
-    constexpr int PANEL = BM * LROW;       // one panel of one plane in LDS
-    constexpr int STAGE = PL * 2 * PANEL;  // A and B panels of every plane
-    constexpr int SEGS = BM * (ROWB / 16) / 256;  // 16-byte global loads per thread per panel
+    constexpr int NB = BM / 32;  // 16x16 blocks per wave side
     typedef typename AccOf<MODE>::type acc_t;
+    static_assert(Ring<MODE>::NS * Ring<MODE>::STAGE >= 4 * NB * NB * 2 * 64 * (int)sizeof(acc_t),
+                  "the ring must hold one group's accumulators for the fold");
 
-    __shared__ __attribute__((aligned(16))) uint8_t smem[2 * STAGE];
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[Ring<MODE>::NS * Ring<MODE>::STAGE];
 
     // ---- which item
     const int item = xcd_remap(blockIdx.x, gridDim.x);
@@ -129,51 +356,9 @@ __global__ __launch_bounds__(256) void herk_kernel(HerkArgs args)
     const int chunk = args.pass * d.nslot + slot;
     int I, J;
     tile_ij(tile, d.ntile, I, J);
-    const bool diag = (I == J);
     const int k0 = chunk * d.chunk;
     const int k1 = min(k0 + d.chunk, d.tpad);
-    const int nst = (k1 - k0) / BKC;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-
-    // ---- global -> LDS staging
-    const int64_t pitch = d.ldu * CB;
-    const uint8_t *ga = d.u + (int64_t)I * BM * pitch + (int64_t)k0 * CB;
-    const uint8_t *gb = d.u + (int64_t)J * BM * pitch + (int64_t)k0 * CB;
-    const int lrow = tid >> 3, lseg = (tid & 7) * 16;
-
-    u32x4 ra[PL][SEGS], rb[PL][SEGS];
-    auto gload = [&](int st) {
-        const int64_t off = (int64_t)st * ROWB + lseg;
-#pragma unroll
-        for (int p = 0; p < PL; ++p)
-#pragma unroll
-            for (int s = 0; s < SEGS; ++s)
-                ra[p][s] = *(const u32x4 *)(ga + p * d.plane_bytes + (int64_t)(lrow + 32 * s) * pitch + off);
-        if (!diag) {
-#pragma unroll
-            for (int p = 0; p < PL; ++p)
-#pragma unroll
-                for (int s = 0; s < SEGS; ++s)
-                    rb[p][s] = *(const u32x4 *)(gb + p * d.plane_bytes + (int64_t)(lrow + 32 * s) * pitch + off);
-        }
-    };
-    auto lstore = [&](int buf) {
-        uint8_t *base = smem + buf * STAGE;
-#pragma unroll
-        for (int p = 0; p < PL; ++p)
-#pragma unroll
-            for (int s = 0; s < SEGS; ++s)
-                *(u32x4 *)(base + p * 2 * PANEL + (lrow + 32 * s) * LROW + lseg) = ra[p][s];
-        if (!diag) {
-#pragma unroll
-            for (int p = 0; p < PL; ++p)
-#pragma unroll
-                for (int s = 0; s < SEGS; ++s)
-                    *(u32x4 *)(base + p * 2 * PANEL + PANEL + (lrow + 32 * s) * LROW + lseg) = rb[p][s];
-        }
-    };
+    const int nst = (k1 - k0) / (RB / cbytes_of(MODE));
 
     acc_t re[NB][NB], im[NB][NB];
 #pragma unroll
@@ -183,113 +368,23 @@ __global__ __launch_bounds__(256) void herk_kernel(HerkArgs args)
             re[a][b] = acc_t{0, 0, 0, 0};
             im[a][b] = acc_t{0, 0, 0, 0};
         }
+    if (I == J)
+        herk_tile<MODE, true>(d, I, J, k0, nst, re, im, smem);
+    else
+        herk_tile<MODE, false>(d, I, J, k0, nst, re, im, smem);
+    fold_groups<MODE>(re, im, smem);
 
-    const int arow = (wm * (BM / 2) + (lane & 15)) * LROW;
-    const int brow = (wn * (BM / 2) + (lane & 15)) * LROW;
-    const int bpanel = diag ? 0 : PANEL;
-
-    auto compute = [&](int buf) {
-        const uint8_t *As = smem + buf * STAGE;
-        const uint8_t *Bs = As + bpanel;
-        if constexpr (CB == 4) {
-            // 16-bit modes: 2 sub-steps of 16 samples (K' = 32 values)
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int off = ks * 64 + (lane >> 4) * 16;
-                u32x4 vb[PL][NB];
-#pragma unroll
-                for (int p = 0; p < PL; ++p)
-#pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        vb[p][b] = *(const u32x4 *)(Bs + p * 2 * PANEL + brow + b * 16 * LROW + off);
-#pragma unroll
-                for (int a = 0; a < NB; ++a) {
-                    u32x4 va[PL], vq[PL];
-#pragma unroll
-                    for (int p = 0; p < PL; ++p) {
-                        va[p] = *(const u32x4 *)(As + p * 2 * PANEL + arow + a * 16 * LROW + off);
-                        vq[p] = swap_neg(va[p]);
-                    }
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        re[a][b] = mfma16<MODE>(va[0], vb[0][b], re[a][b]);
-                        im[a][b] = mfma16<MODE>(vq[0], vb[0][b], im[a][b]);
-                        if constexpr (PL == 2) {
-                            re[a][b] = mfma16<MODE>(va[0], vb[1][b], re[a][b]);
-                            im[a][b] = mfma16<MODE>(vq[0], vb[1][b], im[a][b]);
-                            re[a][b] = mfma16<MODE>(va[1], vb[0][b], re[a][b]);
-                            im[a][b] = mfma16<MODE>(vq[1], vb[0][b], im[a][b]);
-                        }
-                    }
-                }
-            }
-        } else if constexpr (CB == 8) {
-            // FP32: 4 sub-steps of 4 samples; one sample (re, im) per lane
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const int off = ks * 32 + (lane >> 4) * 8;
-                float2 vb[NB];
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    vb[b] = *(const float2 *)(Bs + brow + b * 16 * LROW + off);
-#pragma unroll
-                for (int a = 0; a < NB; ++a) {
-                    const float2 va = *(const float2 *)(As + arow + a * 16 * LROW + off);
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb[b].x, re[a][b], 0, 0, 0);
-                        re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb[b].y, re[a][b], 0, 0, 0);
-                        im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb[b].x, im[a][b], 0, 0, 0);
-                        im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-va.x, vb[b].y, im[a][b], 0, 0, 0);
-                    }
-                }
-            }
-        } else {
-            // FP64: 2 sub-steps of 4 samples; one sample (re, im) per lane
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int off = ks * 64 + (lane >> 4) * 16;
-                double2 vb[NB];
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    vb[b] = *(const double2 *)(Bs + brow + b * 16 * LROW + off);
-#pragma unroll
-                for (int a = 0; a < NB; ++a) {
-                    const double2 va = *(const double2 *)(As + arow + a * 16 * LROW + off);
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.x, vb[b].x, re[a][b], 0, 0, 0);
-                        re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, vb[b].y, re[a][b], 0, 0, 0);
-                        im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, vb[b].x, im[a][b], 0, 0, 0);
-                        im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-va.x, vb[b].y, im[a][b], 0, 0, 0);
-                    }
-                }
-            }
-        }
-    };
-
-    // ---- K loop: double-buffered LDS, one barrier per stage
-    if (nst > 0) {
-        gload(0);
-        lstore(0);
-        __syncthreads();
-        for (int st = 0; st < nst; ++st) {
-            if (st + 1 < nst)
-                gload(st + 1);
-            compute(st & 1);
-            if (st + 1 < nst)
-                lstore((st + 1) & 1);
-            __syncthreads();
-        }
-    }
-
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave >= 4)
+        return;
+    const int wm = wave >> 1, wn = wave & 1;
     // ---- chunk sum of this tile -> partial[slot][tile][re|im][BM][BM] (FP64).
     // A chunk spans at most a few thousand samples, which bounds the FP32
     // accumulation error; later passes over a long T add into the same slot.
     // Accumulator layout of a 16x16 block: lane l, register r holds column
     // l % 16 of row 4 (l / 16) + r for the FP32-output MFMAs, and of row
     // l / 16 + 4 r for v_mfma_f64_16x16x4f64.
-    double *out = d.partial + ((int64_t)slot * d.nupper + tile) * 2 * BM * BM;
+    auto out = gptr(d.partial + ((int64_t)slot * d.nupper + tile) * 2 * BM * BM);
     const int r0 = wm * (BM / 2) + (MODE == M_F64 ? (lane >> 4) : (lane >> 4) * 4);
     constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;
     const int c0 = wn * (BM / 2) + (lane & 15);
@@ -315,7 +410,7 @@ template <int MODE>
 int occupancy_of()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, herk_kernel<MODE>, 256, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, herk_kernel<MODE>, THREADS, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
@@ -327,11 +422,11 @@ hipError_t launch_herk(int mode, const HerkArgs &a, int nwg, hipStream_t s)
     if (nwg <= 0)
         return hipSuccess;
     switch (mode) {
-    case M_F64: herk_kernel<M_F64><<<nwg, 256, 0, s>>>(a); break;
-    case M_F32: herk_kernel<M_F32><<<nwg, 256, 0, s>>>(a); break;
-    case M_SPLIT: herk_kernel<M_SPLIT><<<nwg, 256, 0, s>>>(a); break;
-    case M_BF16: herk_kernel<M_BF16><<<nwg, 256, 0, s>>>(a); break;
-    case M_F16: herk_kernel<M_F16><<<nwg, 256, 0, s>>>(a); break;
+    case M_F64: herk_kernel<M_F64><<<nwg, THREADS, 0, s>>>(a); break;
+    case M_F32: herk_kernel<M_F32><<<nwg, THREADS, 0, s>>>(a); break;
+    case M_SPLIT: herk_kernel<M_SPLIT><<<nwg, THREADS, 0, s>>>(a); break;
+    case M_BF16: herk_kernel<M_BF16><<<nwg, THREADS, 0, s>>>(a); break;
+    case M_F16: herk_kernel<M_F16><<<nwg, THREADS, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -74,26 +74,26 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
     const int s0 = (blockIdx.x * 256 + threadIdx.x) * VEC;
     if (s0 >= a.tpad)
         return;
-    uint8_t *dst = a.u + ((int64_t)row * a.ldu + s0) * cbytes_of(MODE);
+    auto dst = gptr(a.u + ((int64_t)row * a.ldu + s0) * cbytes_of(MODE));
 
     if constexpr (MODE == M_F64) {
-        const double2 *src = (const double2 *)a.in + (int64_t)row * a.ld + a.t0;
-        double2 out[VEC];
+        auto src = gptr((const vd2 *)a.in + (int64_t)row * a.ld + a.t0);
+        vd2 out[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
             const int s = s0 + v;
             double ur = 0.0, ui = 0.0;
             if (s < a.tw) {
-                double2 z = src[s];
+                vd2 z = src[s];
                 unit_phasor(z.x, z.y, ur, ui);
             }
-            out[v] = make_double2(ur, ui);
+            out[v] = vd2{ur, ui};
         }
 #pragma unroll
         for (int v = 0; v < VEC; ++v)
-            ((double2 *)dst)[v] = out[v];
+            ((PLV_GLOBAL vd2 *)dst)[v] = out[v];
     } else {
-        const float2 *src = (const float2 *)a.in + (int64_t)row * a.ld + a.t0;
+        auto src = gptr((const vf2 *)a.in + (int64_t)row * a.ld + a.t0);
         float ur[VEC], ui[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) {
@@ -101,28 +101,20 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
             ur[v] = 0.0f;
             ui[v] = 0.0f;
             if (s < a.tw) {
-                float2 z = src[s];
+                vf2 z = src[s];
                 unit_phasor(z.x, z.y, ur[v], ui[v]);
             }
         }
         if constexpr (MODE == M_F32) {
-            float4 *d = (float4 *)dst;
-            d[0] = make_float4(ur[0], ui[0], ur[1], ui[1]);
-            d[1] = make_float4(ur[2], ui[2], ur[3], ui[3]);
+            auto d = (PLV_GLOBAL vf4 *)dst;
+            d[0] = vf4{ur[0], ui[0], ur[1], ui[1]};
+            d[1] = vf4{ur[2], ui[2], ur[3], ui[3]};
         } else if constexpr (MODE == M_BF16) {
-            uint4 w;
-            w.x = pack_bf16(ur[0], ui[0]);
-            w.y = pack_bf16(ur[1], ui[1]);
-            w.z = pack_bf16(ur[2], ui[2]);
-            w.w = pack_bf16(ur[3], ui[3]);
-            *(uint4 *)dst = w;
+            *(PLV_GLOBAL vu4 *)dst =
+                vu4{pack_bf16(ur[0], ui[0]), pack_bf16(ur[1], ui[1]), pack_bf16(ur[2], ui[2]), pack_bf16(ur[3], ui[3])};
         } else if constexpr (MODE == M_F16) {
-            uint4 w;
-            w.x = pack_f16(ur[0], ui[0]);
-            w.y = pack_f16(ur[1], ui[1]);
-            w.z = pack_f16(ur[2], ui[2]);
-            w.w = pack_f16(ur[3], ui[3]);
-            *(uint4 *)dst = w;
+            *(PLV_GLOBAL vu4 *)dst =
+                vu4{pack_f16(ur[0], ui[0]), pack_f16(ur[1], ui[1]), pack_f16(ur[2], ui[2]), pack_f16(ur[3], ui[3])};
         } else {  // M_SPLIT: hi = rn(u), lo = rn(u - hi); u - hi is exact in FP32
             uint32_t hw[VEC], lw[VEC];
 #pragma unroll
@@ -130,8 +122,8 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
                 hw[v] = pack_bf16(ur[v], ui[v]);
                 lw[v] = pack_bf16(ur[v] - bf16_lo(hw[v]), ui[v] - bf16_hi(hw[v]));
             }
-            *(uint4 *)dst = make_uint4(hw[0], hw[1], hw[2], hw[3]);
-            *(uint4 *)(dst + a.plane_bytes) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+            *(PLV_GLOBAL vu4 *)dst = vu4{hw[0], hw[1], hw[2], hw[3]};
+            *(PLV_GLOBAL vu4 *)(dst + a.plane_bytes) = vu4{lw[0], lw[1], lw[2], lw[3]};
         }
     }
 }

@@ -19,6 +19,28 @@
 
 namespace plv {
 
+// Global-address-space views of device pointers.  Memory accessed through
+// them compiles to global_load / global_store (vector-memory counter only)
+// rather than flat accesses, which also hold the LDS counter.
+template <class T>
+__device__ inline __attribute__((address_space(1))) T *gptr(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T *gptr(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+
+// Native clang vectors (usable through address-space-qualified pointers,
+// unlike HIP's struct vector types).
+typedef float vf2 __attribute__((ext_vector_type(2)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef double vd2 __attribute__((ext_vector_type(2)));
+typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
+#define PLV_GLOBAL __attribute__((address_space(1)))
+
 enum Mode { M_F64 = 0, M_F32 = 1, M_SPLIT = 2, M_BF16 = 3, M_F16 = 4 };
 
 // Tile edge of the Gram kernel for each mode (output tiles are BM x BM).

@@ -2,6 +2,7 @@
 #include "plv_plan.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 
 namespace plv {
@@ -16,20 +17,35 @@ std::string msg(const char *fmt, long long a = 0, long long b = 0)
     return buf;
 }
 
-// K-chunks of a problem computed alone: enough (tile, chunk) items to fill
-// every work-group slot once, no chunk longer than MAX_CHUNK, none shorter
-// than MIN_CHUNK unless T itself is.  Partial slots are capped by
-// PARTIAL_BUDGET; beyond it the chunks run in passes.
+// K-chunks of a problem computed alone.  Every (tile, chunk) item costs about
+// the same, so the launch takes ceil(items / slots) rounds of work-groups; the
+// chunk count is the one that fills those rounds best (fewest chunks among
+// equals), with no chunk longer than MAX_CHUNK and none shorter than MIN_CHUNK
+// unless T itself is.  Partial slots are capped by PARTIAL_BUDGET; beyond it
+// the chunks run in passes.
 void choose_chunks_single(GramPlan &g, int slots, int bm)
 {
     const int kgr = g.tpad / PLV_KGRAN;
-    int nc = 1;
-    if (g.nupper < slots)
-        nc = std::max(1, std::min(kgr, slots / g.nupper));
-    if (nc > 1 && g.tpad / nc < MIN_CHUNK)
-        nc = std::max(1, g.tpad / MIN_CHUNK);
-    nc = std::max(nc, (g.tpad + MAX_CHUNK - 1) / MAX_CHUNK);
-    const int per = (kgr + nc - 1) / nc;  // granules per chunk
+    const int lo = std::max(1, (g.tpad + MAX_CHUNK - 1) / MAX_CHUNK);
+    const int hi = std::max(lo, std::min(kgr, std::max(1, g.tpad / MIN_CHUNK)));
+    int best = lo;
+    double best_eff = -1.0;
+    for (int nc = lo; nc <= hi && nc <= lo + 4 * slots; ++nc) {
+        const int per = (kgr + nc - 1) / nc;
+        const int real_nc = (kgr + per - 1) / per;
+        if (real_nc != nc)
+            continue;
+        const double items = (double)g.nupper * nc;
+        const double rounds = std::ceil(items / slots);
+        const double eff = items / (rounds * slots);
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = nc;
+        }
+        if (eff > 0.97)
+            break;  // good enough: prefer fewer, longer chunks
+    }
+    const int per = (kgr + best - 1) / best;  // granules per chunk
     g.chunk = per * PLV_KGRAN;
     g.nchunk = (kgr + per - 1) / per;
     const size_t slot_bytes = (size_t)g.nupper * 2 * bm * bm * sizeof(double);

@@ -11,7 +11,7 @@
 
 namespace plv {
 
-constexpr int MAX_CHUNK = 8192;      // longest FP32 accumulation span of one work item (samples)
+constexpr int MAX_CHUNK = 16384;     // longest FP32 accumulation span of one work item (samples)
 constexpr int MIN_CHUNK = 1024;      // shortest K-chunk worth a work-group
 constexpr size_t PARTIAL_BUDGET = size_t(2) << 30;  // partial-slot bytes before T is split into passes
 
