@@ -59,6 +59,30 @@ def run_gpu(z, prec, steps, warmup):
     return total_ms / steps, stages
 
 
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("herk.hip", "plv_plan.cpp"):
+        with open(os.path.join(ROOT, "paper_1710_08037_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch recorded from rocprofv3 counters in profiles/traffic.txt,
+    or None when the kernel sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    cur = _source_hash()
+    with open(path) as fh:
+        for line in fh:
+            tok = line.split("#", 1)[0].split()
+            if len(tok) >= 5 and tok[0] == kernel and tok[4] == workload and tok[1] == cur:
+                return int(tok[2]) + int(tok[3])
+    return None
+
+
 def roofline(prec, n, t, stages):
     ms, calls, launches = stages["gram"]
     per_launch_s = ms / max(launches, 1) / 1e3
@@ -66,7 +90,8 @@ def roofline(prec, n, t, stages):
     achieved = flops / per_launch_s / 1e12
     peak = PEAK_TFLOPS[prec]
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
+            "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic("herk_kernel<%s>" % prec, "n%d_t%d" % (n, t)),
             "kernel": "herk_kernel<%s>" % prec, "kernel_ms": round(per_launch_s * 1e3, 4),
             "flop_per_pair_sample": FLOP_PER_PAIR_SAMPLE[prec]}
 
