@@ -24,6 +24,7 @@ SOURCES = [
     "normalise.hip",
     "herk.hip",
     "epilogue.hip",
+    "fft.hip",
 ]
 
 CFLAGS = [

@@ -1,0 +1,96 @@
+// phasor.h -- unit-phasor normalisation (Section II.A, Eq. 4) and the packing of
+// phasors into the Gram kernel's operand formats.  Shared by the kernels that
+// write phasor planes (normalise.hip, fft.hip).
+#pragma once
+
+#include "plv_internal.h"
+
+namespace plv {
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// u = z / |z|, with |z| formed from components rescaled by an exact power of
+// two (no under/overflow for any finite z); z = 0 (either zero sign) -> 1 + 0i,
+// the phasor of angle(0) = 0.  NaN/Inf propagate as NaN.
+__device__ inline void unit_phasor(float re, float im, float &ur, float &ui)
+{
+    if (re == 0.0f && im == 0.0f) {
+        ur = 1.0f;
+        ui = 0.0f;
+        return;
+    }
+    float m = fmaxf(fabsf(re), fabsf(im));
+    int e;
+    (void)frexpf(m, &e);
+    float a = ldexpf(re, -e), b = ldexpf(im, -e);  // exact rescale, max(|a|,|b|) in [0.5, 1)
+    float inv = 1.0f / sqrtf(a * a + b * b);
+    ur = a * inv;
+    ui = b * inv;
+}
+
+__device__ inline void unit_phasor(double re, double im, double &ur, double &ui)
+{
+    if (re == 0.0 && im == 0.0) {
+        ur = 1.0;
+        ui = 0.0;
+        return;
+    }
+    double m = fmax(fabs(re), fabs(im));
+    int e;
+    (void)frexp(m, &e);
+    double a = ldexp(re, -e), b = ldexp(im, -e);
+    double inv = 1.0 / sqrt(a * a + b * b);
+    ur = a * inv;
+    ui = b * inv;
+}
+
+__device__ inline uint32_t pack_bf16(float a, float b)
+{
+    bf16x2 v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ inline uint32_t pack_f16(float a, float b)
+{
+    f16x2 v = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// Stores 4 consecutive phasors (ur[v], ui[v]) of one row at `dst` in the
+// operand format of `MODE` (dst points at sample s0 of plane 0; the split
+// mode's lo plane is plane_bytes further).
+template <int MODE, class R>
+__device__ inline void store4(uint8_t *dst, int64_t plane_bytes, const R (&ur)[4], const R (&ui)[4])
+{
+    if constexpr (MODE == M_F64) {
+        auto d = (PLV_GLOBAL vd2 *)gptr(dst);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            d[v] = vd2{(double)ur[v], (double)ui[v]};
+    } else if constexpr (MODE == M_F32) {
+        auto d = (PLV_GLOBAL vf4 *)gptr(dst);
+        d[0] = vf4{(float)ur[0], (float)ui[0], (float)ur[1], (float)ui[1]};
+        d[1] = vf4{(float)ur[2], (float)ui[2], (float)ur[3], (float)ui[3]};
+    } else if constexpr (MODE == M_BF16) {
+        *(PLV_GLOBAL vu4 *)gptr(dst) = vu4{pack_bf16(ur[0], ui[0]), pack_bf16(ur[1], ui[1]), pack_bf16(ur[2], ui[2]),
+                                          pack_bf16(ur[3], ui[3])};
+    } else if constexpr (MODE == M_F16) {
+        *(PLV_GLOBAL vu4 *)gptr(dst) =
+            vu4{pack_f16(ur[0], ui[0]), pack_f16(ur[1], ui[1]), pack_f16(ur[2], ui[2]), pack_f16(ur[3], ui[3])};
+    } else {  // M_SPLIT: hi = rn(u), lo = rn(u - hi); u - hi is exact in FP32
+        uint32_t hw[4], lw[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            hw[v] = pack_bf16(ur[v], ui[v]);
+            lw[v] = pack_bf16(ur[v] - bf16_lo(hw[v]), ui[v] - bf16_hi(hw[v]));
+        }
+        *(PLV_GLOBAL vu4 *)gptr(dst) = vu4{hw[0], hw[1], hw[2], hw[3]};
+        *(PLV_GLOBAL vu4 *)gptr(dst + plane_bytes) = vu4{lw[0], lw[1], lw[2], lw[3]};
+    }
+}
+
+}  // namespace plv

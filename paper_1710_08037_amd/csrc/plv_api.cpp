@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -286,14 +287,143 @@ static plv_status begin(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_proble
     return PLV_OK;
 }
 
-// Gram + epilogue over every Gram problem of the plan (phasors already in ws).
-static plv_status run_gram(plv_ctx *ctx, const Plan &plan, uint8_t *ws, hipStream_t s)
+// Bins of the band [f_lo, f_hi] for a row of length t: the positive-frequency
+// bins k (0 < k, 2k < t) with f_lo <= k*fs/t <= f_hi, compared in FP64.
+// f_lo = f_hi = 0 selects the plain one-sided weights (klo = -1).
+static BandBins band_bins(int t, double fs, const plv_band *band)
+{
+    if (!band || (band->f_lo == 0.0 && band->f_hi == 0.0))
+        return BandBins{-1, -1};
+    const int kmax = (t - 1) / 2;
+    auto freq = [&](int k) { return (double)k * fs / (double)t; };
+    int klo = std::max(1, (int)std::floor(band->f_lo * t / fs) - 2);
+    while (klo <= kmax && freq(klo) < band->f_lo)
+        ++klo;
+    int khi = std::min(kmax, (int)std::ceil(band->f_hi * t / fs) + 2);
+    while (khi >= 1 && freq(khi) > band->f_hi)
+        --khi;
+    if (klo > khi)
+        return BandBins{1, 0};  // empty band: every weight 0
+    return BandBins{klo, khi};
+}
+
+// Enqueues the whole forward path of a plan on stream s: one upload of the
+// device tables, the front end (normalisation of analytic input, or the FFT
+// analytic signal of real input), the Gram kernel and the epilogue.
+static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_problem *probs, const plv_band *bands,
+                                  int nbands, double fs, uint8_t *ws, hipStream_t s)
 {
     const int mode = plan.mode;
+    const bool real = plan.op == PLV_OP_FROM_REAL;
     std::vector<GramDesc> gd;
     fill_descs(plan, ws, gd);
+    std::vector<Item> items;
+    std::vector<TileRef> tiles;
+    if (plan.grouped)
+        build_tables(plan, gd, items, tiles);
+
+    std::vector<int> class_start, class_count;  // FFT rows per size class
+    if (plan.grouped || real) {
+        std::vector<uint8_t> blob(plan.tables_bytes, 0);
+        memcpy(blob.data() + plan.desc_off, gd.data(), gd.size() * sizeof(GramDesc));
+        if (plan.grouped) {
+            memcpy(blob.data() + plan.item_off, items.data(), items.size() * sizeof(Item));
+            memcpy(blob.data() + plan.tile_off, tiles.data(), tiles.size() * sizeof(TileRef));
+        }
+        if (real) {
+            const size_t nprob = plan.fft.size();
+            HilbertProb *hp = (HilbertProb *)(blob.data() + plan.hp_off);
+            BandBins *bins = (BandBins *)(blob.data() + plan.bin_off);
+            RowRef *rows = (RowRef *)(blob.data() + plan.row_off);
+            ChirpJob *jobs = (ChirpJob *)(blob.data() + plan.job_off);
+            for (size_t q = 0; q < nprob; ++q) {
+                const FftPlan &f = plan.fft[q];
+                const plv_problem &p = probs[q];
+                HilbertProb h{};
+                h.x = p.in;
+                h.ld = p.ld;
+                h.n = (int32_t)p.n;
+                h.t = f.t;
+                h.t0 = (int32_t)p.t0;
+                h.tw = plan.grams[q * nbands].t;
+                h.logm = f.logm;
+                h.blue = f.blue ? 1 : 0;
+                h.chirp = f.blue ? ws + plan.chirp_off[f.chirp_index] : nullptr;
+                h.bhat = f.blue ? ws + plan.bhat_off[f.chirp_index] : nullptr;
+                h.tw_tab = ws + plan.tw_off[f.tw_index];
+                h.gram0 = (int32_t)(q * nbands);
+                h.nbands = nbands;
+                h.bin0 = (int32_t)(q * nbands);
+                hp[q] = h;
+                for (int b = 0; b < nbands; ++b)
+                    bins[q * nbands + b] = band_bins(f.t, fs, bands ? &bands[b] : nullptr);
+            }
+            size_t r = 0;
+            for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+                class_start.push_back((int)r);
+                for (size_t q = 0; q < nprob; ++q)
+                    if (plan.fft[q].logm == plan.tw_logm[c])
+                        for (int64_t i = 0; i < probs[q].n; ++i)
+                            rows[r++] = RowRef{(int32_t)q, (int32_t)i};
+                class_count.push_back((int)r - class_start.back());
+            }
+            for (size_t c = 0; c < plan.chirp_t.size(); ++c)
+                jobs[c] = ChirpJob{plan.chirp_t[c], plan.chirp_logm[c], ws + plan.chirp_off[c], ws + plan.bhat_off[c]};
+        }
+        plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
+        if (st != PLV_OK)
+            return st;
+    }
+
     hipError_t e;
-    if (gd.size() == 1) {
+    if (real) {
+        StageTimer tm(ctx, PLV_STAGE_HILBERT, s);
+        const bool f64 = mode == M_F64;
+        for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+            if ((e = launch_twiddles(f64, ws + plan.tw_off[c], plan.tw_logm[c], s)) != hipSuccess)
+                return hip_fail(ctx, e, "twiddle kernel launch");
+            tm.launched();
+        }
+        if (!plan.chirp_t.empty()) {
+            if ((e = launch_chirps(f64, (const ChirpJob *)(ws + plan.job_off), (int)plan.chirp_t.size(), s)) !=
+                hipSuccess)
+                return hip_fail(ctx, e, "chirp kernel launch");
+            tm.launched();
+        }
+        for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+            HilbertArgs ha{};
+            ha.hp = (const HilbertProb *)(ws + plan.hp_off);
+            ha.bins = (const BandBins *)(ws + plan.bin_off);
+            ha.rows = (const RowRef *)(ws + plan.row_off) + class_start[c];
+            ha.nrows = class_count[c];
+            ha.logm = plan.tw_logm[c];
+            ha.gd = (const GramDesc *)(ws + plan.desc_off);
+            const int nwg = std::min(class_count[c], ctx->cus);
+            if ((e = launch_hilbert(mode, ha, nwg, s)) != hipSuccess)
+                return hip_fail(ctx, e, "analytic-signal kernel launch");
+            tm.launched();
+        }
+    } else {
+        StageTimer tm(ctx, PLV_STAGE_NORMALISE, s);
+        for (const GramPlan &gp : plan.grams) {
+            const plv_problem &p = probs[gp.prob];
+            NormArgs na{};
+            na.in = p.in;
+            na.ld = p.ld;
+            na.t0 = gp.t0;
+            na.tw = gp.t;
+            na.n = gp.n;
+            na.u = ws + gp.u_off;
+            na.plane_bytes = (int64_t)gp.plane_bytes;
+            na.ldu = gp.tpad;
+            na.tpad = gp.tpad;
+            if ((e = launch_normalise(mode, na, s)) != hipSuccess)
+                return hip_fail(ctx, e, "normalise kernel launch");
+            tm.launched();
+        }
+    }
+
+    if (!plan.grouped) {
         const GramDesc &d = gd[0];
         const int passes = (d.nchunk + d.nslot - 1) / d.nslot;
         {
@@ -310,23 +440,12 @@ static plv_status run_gram(plv_ctx *ctx, const Plan &plan, uint8_t *ws, hipStrea
         }
         StageTimer tm(ctx, PLV_STAGE_EPILOGUE, s);
         EpiArgs ea{};
-        ea.g = gd[0];
-        if ((e = launch_epilogue(mode, ea, gd[0].nupper, s)) != hipSuccess)
+        ea.g = d;
+        if ((e = launch_epilogue(mode, ea, d.nupper, s)) != hipSuccess)
             return hip_fail(ctx, e, "epilogue kernel launch");
         tm.launched();
         return PLV_OK;
     }
-    std::vector<uint8_t> blob;
-    std::vector<Item> items;
-    std::vector<TileRef> tiles;
-    build_tables(plan, gd, items, tiles);
-    blob.resize(plan.tables_bytes, 0);
-    memcpy(blob.data() + plan.desc_off - plan.tables_off, gd.data(), gd.size() * sizeof(GramDesc));
-    memcpy(blob.data() + plan.item_off - plan.tables_off, items.data(), items.size() * sizeof(Item));
-    memcpy(blob.data() + plan.tile_off - plan.tables_off, tiles.data(), tiles.size() * sizeof(TileRef));
-    plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
-    if (st != PLV_OK)
-        return st;
     HerkArgs ha{};
     ha.gd = (const GramDesc *)(ws + plan.desc_off);
     ha.items = (const Item *)(ws + plan.item_off);
@@ -354,41 +473,24 @@ plv_status plv_from_analytic(plv_ctx *ctx, plv_prec prec, const plv_problem *pro
     plv_status st = begin(ctx, PLV_OP_FROM_ANALYTIC, prec, probs, nprob, nullptr, 1, ws, ws_bytes, plan);
     if (st != PLV_OK)
         return st;
-    hipStream_t s = (hipStream_t)stream;
-    uint8_t *w = (uint8_t *)ws;
-    {
-    StageTimer tm(ctx, PLV_STAGE_NORMALISE, s);
-    for (const GramPlan &gp : plan.grams) {
-        const plv_problem &p = probs[gp.prob];
-        NormArgs na{};
-        na.in = p.in;
-        na.ld = p.ld;
-        na.t0 = gp.t0;
-        na.tw = gp.t;
-        na.n = gp.n;
-        na.u = w + gp.u_off;
-        na.plane_bytes = (int64_t)gp.plane_bytes;
-        na.ldu = gp.tpad;
-        na.tpad = gp.tpad;
-        hipError_t e = launch_normalise(plan.mode, na, s);
-        if (e != hipSuccess)
-            return hip_fail(ctx, e, "normalise kernel launch");
-        tm.launched();
-    }
-    }
-    return run_gram(ctx, plan, w, s);
+    return enqueue_forward(ctx, plan, probs, nullptr, 1, 0.0, (uint8_t *)ws, (hipStream_t)stream);
 }
 
 plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
                          const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes, void *stream)
 {
-    (void)fs;
+    if (!ctx)
+        return PLV_ERR_INVALID_ARG;
+    if (bands) {
+        for (int32_t b = 0; b < nbands; ++b)
+            if ((bands[b].f_lo != 0.0 || bands[b].f_hi != 0.0) && !(fs > 0.0 && std::isfinite(fs)))
+                return fail(ctx, PLV_ERR_INVALID_ARG, "a band-pass band needs a finite sampling rate fs > 0");
+    }
     Plan plan;
     plv_status st = begin(ctx, PLV_OP_FROM_REAL, prec, probs, nprob, bands, nbands, ws, ws_bytes, plan);
     if (st != PLV_OK)
         return st;
-    (void)stream;
-    return fail(ctx, PLV_ERR_UNSUPPORTED, "plv_from_real: not built yet");
+    return enqueue_forward(ctx, plan, probs, bands, bands ? nbands : 1, fs, (uint8_t *)ws, (hipStream_t)stream);
 }
 
 plv_status plv_backward(plv_ctx *ctx, plv_prec prec, plv_input kind, const plv_problem *probs,

@@ -103,6 +103,50 @@ struct NormArgs {
     int32_t tpad;
 };
 
+// ------------------------------------------------- analytic signal (FFT) --
+// One problem of real rows, transformed at its own length t through an FFT of
+// size M = 2^logm (M = t for a power-of-two t; otherwise Bluestein, M >= 2t-1).
+struct HilbertProb {
+    const void *x;       // real rows [n][ld] (f32; f64 in F64 mode)
+    int64_t ld;
+    int32_t n, t;        // rows, DFT length
+    int32_t t0, tw;      // window start and length (samples that enter the Gram)
+    int32_t logm, blue;  // FFT size; 1 = Bluestein
+    const void *chirp;   // [t] complex c_m = exp(i pi m^2 / t) (Bluestein)
+    const void *bhat;    // [M] complex FFT_M of the circular chirp (Bluestein)
+    const void *tw_tab;  // [M/2] complex exp(-2 pi i k / M)
+    int32_t gram0;       // Gram problem of band 0 (band b -> gram0 + b)
+    int32_t nbands;
+    int32_t bin0;        // first entry of this problem in the band-bin table
+    int32_t pad_;
+};
+
+// Positive-frequency bins [klo, khi] that get weight 2; klo < 0 selects the
+// plain one-sided weights (1 at DC, 2 below Nyquist, 1 at Nyquist, 0 above).
+struct BandBins {
+    int32_t klo, khi;
+};
+
+struct RowRef {
+    int32_t prob, row;
+};
+
+struct HilbertArgs {
+    const HilbertProb *hp;
+    const BandBins *bins;
+    const RowRef *rows;   // rows of this launch (all share logm)
+    int32_t nrows;
+    int32_t logm;
+    const GramDesc *gd;   // destinations of the phasor planes
+};
+
+// Bluestein set-up for one distinct length t.
+struct ChirpJob {
+    int32_t t, logm;
+    void *chirp;          // [t] complex
+    void *bhat;           // [M] complex (written as the circular chirp, then transformed in place)
+};
+
 // -------------------------------------------------------------- launchers --
 // Each returns hipSuccess or the launch error.
 hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s);
@@ -110,5 +154,11 @@ hipError_t launch_herk(int mode, const HerkArgs &a, int nwg, hipStream_t s);
 hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, hipStream_t s);
 // Occupancy (work-groups per CU) of the Gram kernel of `mode`.
 int herk_occupancy(int mode);
+// FFT stage (fft.hip).  f64 selects double precision tables and transforms.
+constexpr int FFT_MAXLOG_F32 = 13;  // M <= 8192 complex FP32 transforms in LDS
+constexpr int FFT_MAXLOG_F64 = 12;  // M <= 4096 complex FP64
+hipError_t launch_twiddles(bool f64, void *tab, int logm, hipStream_t s);
+hipError_t launch_chirps(bool f64, const ChirpJob *jobs, int njobs, hipStream_t s);
+hipError_t launch_hilbert(int mode, const HilbertArgs &a, int nwg, hipStream_t s);
 
 }  // namespace plv

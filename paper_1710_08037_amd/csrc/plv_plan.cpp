@@ -169,7 +169,13 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
 
     const int slots = std::max(1, cus) * std::max(1, occ ? occ[mode] : 1);
     const bool grouped = plan.grams.size() > 1;
+    plan.grouped = grouped;
+    // device tables: Gram problem descriptors always (the FFT stage reads them
+    // too); items and tiles for a grouped launch; FFT tables for real input.
     size_t off = 0;
+    plan.tables_off = 0;
+    plan.desc_off = 0;
+    off = align256(plan.grams.size() * sizeof(GramDesc));
     if (grouped) {
         for (GramPlan &g : plan.grams)
             choose_chunks_grouped(g);
@@ -181,14 +187,65 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
             why = "too many work items";
             return PLV_ERR_INVALID_ARG;
         }
-        plan.tables_off = 0;
-        plan.desc_off = 0;
-        plan.item_off = align256(plan.grams.size() * sizeof(GramDesc));
-        plan.tile_off = plan.item_off + align256(plan.nitems * sizeof(Item));
-        plan.tables_bytes = plan.tile_off + align256(plan.ntiles * sizeof(TileRef));
-        off = plan.tables_bytes;
+        plan.item_off = off;
+        off += align256(plan.nitems * sizeof(Item));
+        plan.tile_off = off;
+        off += align256(plan.ntiles * sizeof(TileRef));
     } else {
         choose_chunks_single(plan.grams[0], slots, bm);
+    }
+    if (real) {
+        const int maxlog = mode == M_F64 ? FFT_MAXLOG_F64 : FFT_MAXLOG_F32;
+        const size_t csz = mode == M_F64 ? 16 : 8;
+        plan.fft.resize((size_t)nprob);
+        for (int64_t q = 0; q < nprob; ++q) {
+            FftPlan &f = plan.fft[q];
+            f.t = (int)probs[q].t;
+            const bool pow2 = f.t >= 2 && (f.t & (f.t - 1)) == 0;
+            f.blue = !pow2;
+            int need = pow2 ? f.t : std::max(2, 2 * f.t - 1);
+            f.logm = 0;
+            while ((1 << f.logm) < need)
+                ++f.logm;
+            if (f.logm > maxlog) {
+                why = msg("problem %lld: row length %lld is beyond the FFT stage's LDS-resident sizes", q, f.t);
+                return PLV_ERR_UNSUPPORTED;
+            }
+            auto it = std::find(plan.tw_logm.begin(), plan.tw_logm.end(), f.logm);
+            f.tw_index = (int)(it - plan.tw_logm.begin());
+            if (it == plan.tw_logm.end())
+                plan.tw_logm.push_back(f.logm);
+            if (f.blue) {
+                auto jt = std::find(plan.chirp_t.begin(), plan.chirp_t.end(), f.t);
+                f.chirp_index = (int)(jt - plan.chirp_t.begin());
+                if (jt == plan.chirp_t.end()) {
+                    plan.chirp_t.push_back(f.t);
+                    plan.chirp_logm.push_back(f.logm);
+                }
+            }
+            plan.nrows += (size_t)probs[q].n;
+        }
+        plan.hp_off = off;
+        off += align256((size_t)nprob * sizeof(HilbertProb));
+        plan.bin_off = off;
+        off += align256((size_t)nprob * nbands * sizeof(BandBins));
+        plan.row_off = off;
+        off += align256(plan.nrows * sizeof(RowRef));
+        plan.job_off = off;
+        off += align256(plan.chirp_t.size() * sizeof(ChirpJob));
+        plan.tables_bytes = off;
+        for (int lg : plan.tw_logm) {
+            plan.tw_off.push_back(off);
+            off += align256((size_t)(1 << lg) / 2 * csz);
+        }
+        for (size_t c = 0; c < plan.chirp_t.size(); ++c) {
+            plan.chirp_off.push_back(off);
+            off += align256((size_t)plan.chirp_t[c] * csz);
+            plan.bhat_off.push_back(off);
+            off += align256((size_t)(1 << plan.chirp_logm[c]) * csz);
+        }
+    } else {
+        plan.tables_bytes = off;
     }
     for (GramPlan &g : plan.grams) {
         g.plane_bytes = align256((size_t)g.npad * g.tpad * cb);

@@ -27,13 +27,30 @@ struct GramPlan {
     void *plv = nullptr, *iplv = nullptr, *ciplv = nullptr, *g = nullptr;
 };
 
+// FFT stage of one real-input problem.
+struct FftPlan {
+    int t = 0, logm = 0;
+    bool blue = false;
+    int tw_index = 0;     // which twiddle table (by logm)
+    int chirp_index = -1; // which Bluestein set-up (by t), or -1
+};
+
 struct Plan {
     int mode = 0;
     plv_op op = PLV_OP_FROM_ANALYTIC;
     std::vector<GramPlan> grams;
-    size_t tables_off = 0, tables_bytes = 0;  // device work tables (grouped launch only)
+    size_t tables_off = 0, tables_bytes = 0;  // device tables, uploaded once per call
     size_t desc_off = 0, item_off = 0, tile_off = 0;
     size_t nitems = 0, ntiles = 0;
+    bool grouped = false;                     // Gram work from the item table
+    // real input only
+    std::vector<FftPlan> fft;                 // per problem
+    std::vector<int> tw_logm;                 // distinct FFT sizes
+    std::vector<size_t> tw_off;
+    std::vector<int> chirp_t, chirp_logm;     // distinct Bluestein lengths
+    std::vector<size_t> chirp_off, bhat_off;
+    size_t hp_off = 0, bin_off = 0, row_off = 0, job_off = 0;
+    size_t nrows = 0;
     size_t total = 0;
 };
 

@@ -1,0 +1,134 @@
+"""GPU parity of plv_from_real (FFT analytic signal on the GPU, Eq. 3) against
+the FP64 oracle (plain-DFT analytic signal, per-pair angle/exp/mean), element
+by element on the same seeded real inputs.
+
+Tolerances are those of the analytic-input tests: the transform's own
+rounding (FP64 or FP32 FFT) is far below them for these signals.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.test_gpu_parity import TOL, compare, cond_ciplv
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def plv_mod():
+    import paper_1710_08037_amd as plv
+    return plv
+
+
+def real_dev(x, prec):
+    dt = np.float64 if prec == "f64" else np.float32
+    return torch.from_numpy(np.ascontiguousarray(x.astype(dt))).cuda()
+
+
+def exact_real(x, prec):
+    return x.astype(np.float64 if prec == "f64" else np.float32).astype(np.float64)
+
+
+def fits_lds_fft(t, prec):
+    """The FFT stage keeps a row's transforms in LDS: M <= 8192 (FP32 modes) or
+    4096 (FP64), M = t for a power of two, else the power of two >= 2t - 1."""
+    m = t if (t >= 2 and t & (t - 1) == 0) else 1 << max(1, (2 * t - 2).bit_length())
+    return m <= (4096 if prec == "f64" else 8192)
+
+
+def to_np(out, b):
+    return {k: v[b].cpu().numpy().astype(np.complex128 if k == "g" else np.float64) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16", "bf16", "f16"])
+def test_small_lagged_oscillators_plain_analytic_signal(prec):
+    """N = 64 real signals, T = 2048 samples at fs = 256 Hz, 8 latent 10 Hz
+    oscillators (the small end-to-end case), plain analytic signal."""
+    x = synth.glag_real(64, 2048, 256.0, 8, 10.0, seed=synth.seed_for(1))
+    out = plv_mod().from_real(real_dev(x, prec), 256.0, prec=prec, want_g=True)
+    torch.cuda.synchronize()
+    ref = oracle.full_from_real(exact_real(x, prec))
+    compare(to_np(out, 0), ref, TOL[prec], "small plain %s" % prec)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16"])
+@pytest.mark.parametrize("t", [1, 2, 3, 97, 500, 777, 1000, 997, 4000])
+def test_bluestein_and_radix2_lengths(prec, t):
+    n = 19
+    x = synth.glag_real(n, t, 1000.0, 3, (8, 12), seed=300 + t)
+    if not fits_lds_fft(t, prec):
+        from paper_1710_08037_amd._abi import PLVError
+        with pytest.raises(PLVError, match="UNSUPPORTED"):
+            plv_mod().from_real(real_dev(x, prec), 1000.0, prec=prec)
+        return
+    out = plv_mod().from_real(real_dev(x, prec), 1000.0, prec=prec, want_g=True)
+    torch.cuda.synchronize()
+    ref = oracle.full_from_real(exact_real(x, prec))
+    compare(to_np(out, 0), ref, TOL[prec], "t=%d %s" % (t, prec))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16"])
+@pytest.mark.parametrize("t", [2000, 2048, 3001])
+def test_bands_and_window(prec, t):
+    n, fs = 23, 1000.0
+    bands = [(8.0, 12.0), (0.0, 0.0), (18.0, 22.0), (10.0, 10.0)]
+    x = synth.glag_real(n, t, fs, 4, (8, 22), seed=400 + t)
+    win = (150, t - 170)
+    if not fits_lds_fft(t, prec):
+        from paper_1710_08037_amd._abi import PLVError
+        with pytest.raises(PLVError, match="UNSUPPORTED"):
+            plv_mod().from_real(real_dev(x, prec), fs, bands=bands, prec=prec, window=win)
+        return
+    out = plv_mod().from_real(real_dev(x, prec), fs, bands=bands, prec=prec, window=win, want_g=True)
+    torch.cuda.synchronize()
+    xr = exact_real(x, prec)
+    for b, band in enumerate(bands):
+        ref = oracle.full_from_real(xr, fs, None if band == (0.0, 0.0) else band, window=win)
+        compare(to_np(out, b), ref, TOL[prec], "t=%d band %s %s" % (t, band, prec))
+
+
+@pytest.mark.parametrize("prec", ["f32", "split_bf16", "f64"])
+def test_grouped_uneven_problems_with_bands(prec):
+    """Several trials of uneven N and T in one call, five bands each (the
+    uneven-batch workload in miniature)."""
+    fs = 1000.0
+    bands = synth.bands_hz()
+    shapes = [(68, 700), (148, 1024), (5, 999), (40, 2500), (68, 4000)]
+    if prec == "f64":   # FP64 rows must fit a 4096-point transform
+        shapes = [(68, 700), (148, 1024), (5, 999), (40, 2048), (30, 1500)]
+    xs = [synth.glag_real(n, t, fs, 4, (2, 42), seed=500 + k) for k, (n, t) in enumerate(shapes)]
+    outs = plv_mod().from_real_batch([real_dev(x, prec) for x in xs], fs, bands=bands, prec=prec, want_g=True)
+    torch.cuda.synchronize()
+    for k, x in enumerate(xs):
+        xr = exact_real(x, prec)
+        for b, band in enumerate(bands):
+            ref = oracle.full_from_real(xr, fs, band)
+            compare(to_np(outs[k], b), ref, TOL[prec], "problem %d band %d" % (k, b))
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "f32"])
+def test_differentiable_case_size_sampled_rows(prec):
+    """N = 2048 real signals of T = 8192 samples at 1 kHz, 32 latents: the
+    full-size forward of the differentiable case, checked on all pairs among
+    sampled rows (the analytic signal is per row, so the oracle needs only
+    those rows) and on global properties."""
+    n, t, fs = 2048, 8192, 1000.0
+    x = synth.glag_real(n, t, fs, 32, (8, 12), seed=synth.seed_for(5))
+    out = plv_mod().from_real(real_dev(x, prec), fs, prec=prec, want_g=True)
+    torch.cuda.synchronize()
+    got = to_np(out, 0)
+    rng = np.random.default_rng(8)
+    rows = np.sort(rng.choice(n, size=24, replace=False))
+    ref = oracle.full_from_real(exact_real(x[rows], prec))
+    sub = {k: v[np.ix_(rows, rows)] for k, v in got.items()}
+    compare(sub, ref, TOL[prec], "sampled rows")
+    assert np.array_equal(got["plv"], got["plv"].T)
+    assert abs(np.trace(got["g"]).real - n) <= n * TOL[prec]
+
+
+def test_band_needs_sampling_rate():
+    from paper_1710_08037_amd._abi import PLVError
+    x = real_dev(synth.glag_real(4, 64, 100.0, 2, 10.0, seed=1), "f32")
+    with pytest.raises(PLVError):
+        plv_mod().from_real(x, 0.0, bands=[(8.0, 12.0)], prec="f32")
