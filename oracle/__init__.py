@@ -76,6 +76,8 @@ def lib():
             L.oracle_phase_grad.argtypes = [_D, C.c_int64, C.c_int64, C.c_int64, _D, _D, _D, C.c_int64,
                                             C.c_int]
             L.oracle_phase_to_z.argtypes = [_D, _D, _D, C.c_int64, _D, _D]
+            L.oracle_phase_grad_rows.argtypes = [_D, C.c_int64, C.c_int64, C.c_int64, _D, _D, _I, C.c_int64, _D,
+                                                 C.c_int64, C.c_int]
             _LIB = L
     return _LIB
 
@@ -140,6 +142,16 @@ def analytic(x: np.ndarray, fs: float | None = None, band=None, nthreads=None) -
     t = x.shape[1]
     h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
     return spectral_filter(x, h, nthreads)
+
+
+def analytic_fft(x: np.ndarray, fs: float | None = None, band=None) -> np.ndarray:
+    """The same analytic signal as ``analytic`` with numpy's FFT as the DFT
+    (a library primitive; pinned against the plain-DFT sums), for rows too
+    long or too many for O(T^2) sums."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    t = x.shape[1]
+    h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
+    return np.fft.ifft(h * np.fft.fft(x, axis=-1), axis=-1)
 
 
 # --------------------------------------------------------------------------
@@ -296,4 +308,49 @@ def grad_from_real(x: np.ndarray, fs=None, band=None, gp=None, gi=None, gc=None,
     h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
     z = spectral_filter(x, h, nthreads)
     zbar = grad_from_analytic(z, gp, gi, gc, window, nthreads)
+    return spectral_filter(zbar, h, nthreads).real
+
+
+def grad_from_real_rows(x: np.ndarray, rows, fs=None, band=None, gp=None, gi=None, gc=None, window=None,
+                        nthreads=None) -> np.ndarray:
+    """dL/dx for the listed rows only, [len(rows), T], same chain as
+    ``grad_from_real``.  The analytic signal of every row comes from
+    ``analytic_fft``; the pair sums run only over pairs that touch the rows."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    n, t = x.shape
+    rows = np.asarray(rows, dtype=np.int64)
+    w0, w1 = (0, t) if window is None else window
+    z = analytic_fft(x, fs, band)
+    zw = np.ascontiguousarray(z[:, w0:w1])
+    tw = w1 - w0
+    phi = phase(zw)
+    # G and the metric adjoint for every pair that touches a listed row
+    sel = np.zeros(n, dtype=bool)
+    sel[rows] = True
+    a_idx, b_idx = np.triu_indices(n, 1)
+    keep = sel[a_idx] | sel[b_idx]
+    pr = np.stack([a_idx[keep], b_idx[keep]], 1)
+    g = pair_means(phi, pr, nthreads)
+    upp, upi, upc = _pair_upstream(gp, gi, gc, n)
+    dre = np.zeros((n, n))
+    dim = np.zeros((n, n))
+    zz = np.zeros(len(pr))
+    gr_, gi_ = _f64(g.real), _f64(g.imag)
+    vals = [(_f64(u[pr[:, 0], pr[:, 1]]) if u is not None else zz) for u in (upp, upi, upc)]
+    ore = np.empty(len(pr))
+    oim = np.empty(len(pr))
+    lib().oracle_metric_adjoint(_p(gr_), _p(gi_), _p(vals[0]), _p(vals[1]), _p(vals[2]), len(pr), _p(ore),
+                                _p(oim))
+    dre[pr[:, 0], pr[:, 1]] = ore
+    dim[pr[:, 0], pr[:, 1]] = oim
+    dphi = np.empty((len(rows), tw))
+    lib().oracle_phase_grad_rows(_p(phi), tw, n, tw, _p(dre), _p(dim), rows.ctypes.data_as(_I), len(rows), _p(dphi),
+                                 tw, int(nthreads or threads()))
+    zr, zi = _f64(zw[rows].real), _f64(zw[rows].imag)
+    dzr = np.empty(zr.shape)
+    dzi = np.empty(zr.shape)
+    lib().oracle_phase_to_z(_p(zr), _p(zi), _p(dphi), zr.size, _p(dzr), _p(dzi))
+    zbar = np.zeros((len(rows), t), dtype=np.complex128)
+    zbar[:, w0:w1] = dzr + 1j * dzi
+    h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
     return spectral_filter(zbar, h, nthreads).real

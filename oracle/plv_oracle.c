@@ -366,6 +366,74 @@ static void *grad_worker(void *arg)
     return NULL;
 }
 
+/* dL/dphi of the listed rows only (rows[r] -> dphi row r), same sums as
+ * oracle_phase_grad. */
+struct grad_rows_job {
+    struct grad_job base;
+    const int64_t *rows;
+};
+
+static void *grad_rows_worker(void *arg)
+{
+    struct grad_rows_job *rj = (struct grad_rows_job *)arg;
+    struct grad_job *jb = &rj->base;
+    const int64_t n = jb->n, t = jb->t;
+    const double inv_t = 1.0 / (double)t;
+    for (int64_t r = jb->r0; r < jb->r1; ++r) {
+        const int64_t i = rj->rows[r];
+        double *out = jb->dphi + r * jb->ldd;
+        for (int64_t s = 0; s < t; ++s)
+            out[s] = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i)
+                continue;
+            int64_t a = i < j ? i : j, b = i < j ? j : i;
+            double gr = jb->dre[a * n + b], gm = jb->dim[a * n + b];
+            if (gr == 0.0 && gm == 0.0)
+                continue;
+            double sign = (i == a) ? 1.0 : -1.0;
+            const double *pa = jb->phi + a * jb->ld, *pb = jb->phi + b * jb->ld;
+            for (int64_t s = 0; s < t; ++s) {
+                double d = pa[s] - pb[s];
+                out[s] += sign * (gr * (-sin(d)) + gm * cos(d)) * inv_t;
+            }
+        }
+    }
+    return NULL;
+}
+
+void oracle_phase_grad_rows(const double *phi, int64_t ld, int64_t n, int64_t t, const double *dre,
+                            const double *dim, const int64_t *rows, int64_t nrows, double *dphi, int64_t ldd,
+                            int nthreads)
+{
+    if (nrows <= 0)
+        return;
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > nrows)
+        nthreads = (int)nrows;
+    if (nthreads > 256)
+        nthreads = 256;
+    struct grad_rows_job jobs[256];
+    pthread_t th[256];
+    for (int w = 0; w < nthreads; ++w) {
+        jobs[w].base.phi = phi;
+        jobs[w].base.ld = ld;
+        jobs[w].base.n = n;
+        jobs[w].base.t = t;
+        jobs[w].base.dre = dre;
+        jobs[w].base.dim = dim;
+        jobs[w].base.dphi = dphi;
+        jobs[w].base.ldd = ldd;
+        jobs[w].base.r0 = nrows * w / nthreads;
+        jobs[w].base.r1 = nrows * (w + 1) / nthreads;
+        jobs[w].rows = rows;
+        pthread_create(&th[w], NULL, grad_rows_worker, &jobs[w]);
+    }
+    for (int w = 0; w < nthreads; ++w)
+        pthread_join(th[w], NULL);
+}
+
 /* dL/dphi for every row, from per-pair dL/dRe G and dL/dIm G stored in the
  * upper triangle of [n][n] arrays. */
 void oracle_phase_grad(const double *phi, int64_t ld, int64_t n, int64_t t, const double *dre, const double *dim,

@@ -166,3 +166,70 @@ def timing_read(reset=True, device=None):
     t = _abi.Timing()
     _abi.check(_abi.lib().plv_timing_read(ctx.handle, C.byref(t), 1 if reset else 0), ctx.handle)
     return {name: (t.ms[k], t.calls[k], t.launches[k]) for k, name in enumerate(_abi.STAGES)}
+
+
+def backward_batch(xs, gs, upstream, fs=None, bands=None, prec="split_bf16", windows=None):
+    """dL/d(input) for each problem through plv_backward.
+
+    xs: the forward inputs (complex analytic or real rows); gs: the forward's
+    complex G per problem ([n, n] or [nbands, n, n]); upstream: per problem a
+    tuple (dL/dplv, dL/diplv, dL/dciplv), each a tensor shaped like the
+    outputs or None.  Returns tensors shaped like xs.
+    """
+    p = _prec_id(prec)
+    dev = xs[0].device
+    real = not xs[0].is_complex()
+    barr, nb = _abi.bands(bands) if real else (None, 1)
+    probs, grads, dins, keep = [], [], [], []
+    for k, x in enumerate(xs):
+        n, t, ld = _rows(x)
+        w = None if windows is None else windows[k]
+        t0, t1 = (0, 0) if w is None else (int(w[0]), int(w[1]))
+        g = gs[k].contiguous()
+        ups = [None if u is None else u.contiguous() for u in upstream[k]]
+        # same layout and row stride as the input (the ABI writes din with in's ld)
+        din = torch.empty_strided(x.size(), x.stride(), dtype=x.dtype, device=x.device)
+        keep += [g, din] + ups
+        probs.append(_abi.Problem(n, t, ld, t0, t1, x.data_ptr(), None, None, None, g.data_ptr()))
+        grads.append(_abi.Grad(*(_ptr(u) for u in ups), din.data_ptr()))
+        dins.append(din)
+    arr = _abi.problems(probs)
+    garr = (_abi.Grad * len(grads))(*grads)
+    ctx = context(dev)
+    op = _abi.OP_BACKWARD_REAL if real else _abi.OP_BACKWARD_ANALYTIC
+    ws = _workspace(ctx, op, p, arr, barr, nb, dev)
+    kind = _abi.INPUT_REAL if real else _abi.INPUT_ANALYTIC
+    _abi.check(_abi.lib().plv_backward(ctx.handle, p, kind, arr, garr, len(probs), barr, nb,
+                                       float(fs or 0.0), C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev)),
+               ctx.handle)
+    return dins
+
+
+class PLVFunction(torch.autograd.Function):
+    """(plv, iplv, ciplv) of one problem with the library's adjoint as backward.
+
+    Analytic (complex) input gives [n, n] outputs; real input gives
+    [nbands, n, n] (one plain band when `bands` is None)."""
+
+    @staticmethod
+    def forward(ctx, x, fs, bands, prec, window):
+        if x.is_complex():
+            out = from_analytic(x, prec=prec, window=window, want_g=True)
+        else:
+            out = from_real(x, fs, bands=bands, prec=prec, window=window, want_g=True)
+        ctx.save_for_backward(x, out["g"])
+        ctx.cfg = (fs, bands, prec, window)
+        return out["plv"], out["iplv"], out["ciplv"]
+
+    @staticmethod
+    def backward(ctx, gp, gi, gc):
+        x, g = ctx.saved_tensors
+        fs, bands, prec, window = ctx.cfg
+        din = backward_batch([x], [g], [(gp, gi, gc)], fs=fs, bands=bands, prec=prec,
+                             windows=None if window is None else [window])[0]
+        return din, None, None, None, None
+
+
+def plv_metrics(x, fs=None, bands=None, prec="split_bf16", window=None):
+    """Differentiable (plv, iplv, ciplv) of x (complex analytic or real rows)."""
+    return PLVFunction.apply(x, fs, bands, prec, window)

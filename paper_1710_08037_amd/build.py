@@ -25,6 +25,7 @@ SOURCES = [
     "herk.hip",
     "epilogue.hip",
     "fft.hip",
+    "backward.hip",
 ]
 
 CFLAGS = [

@@ -228,6 +228,19 @@ __global__ __launch_bounds__(NT) void hilbert_kernel(HilbertArgs a)
                 zscale = (R)1 / ((R)M * (R)t);
             }
             const GramDesc g = a.gd[hp.gram0 + b];
+            if (g.zbuf) {
+                // backward: keep the analytic signal itself on the window
+                cx<R> *zr = (cx<R> *)g.zbuf + (int64_t)rr.row * g.ldz;
+                for (int s = threadIdx.x; s < hp.tw; s += NT) {
+                    const int n = hp.t0 + s;
+                    cx<R> z = W[brev(n, logm)];
+                    if (hp.blue)
+                        z = cmul(ch[n], cconj(z));
+                    zr[s] = cscale(z, zscale);
+                }
+                __syncthreads();
+                continue;
+            }
             uint8_t *urow = (uint8_t *)g.u + (int64_t)rr.row * g.ldu * cbytes_of(MODE);
             for (int s0 = threadIdx.x * 4; s0 < g.tpad; s0 += NT * 4) {
                 R ur[4], ui[4];
@@ -251,7 +264,115 @@ __global__ __launch_bounds__(NT) void hilbert_kernel(HilbertArgs a)
     }
 }
 
+// dL/dx of one row: z_b = M_b x with M_b = IDFT diag(h_b) DFT Hermitian
+// (h_b real), so dL/dx = Re(sum_b M_b zbar_b) = Re(IDFT(sum_b h_b .*
+// DFT(zbar_b))), zbar_b being 0 outside the window.
+template <class R, int MAXLOG>
+__global__ __launch_bounds__(NT) void hilbert_adjoint_kernel(HilbertArgs a)
+{
+    __shared__ cx<R> X[1 << MAXLOG];   // sum over bands of h_b .* DFT(zbar_b)
+    __shared__ cx<R> W[1 << MAXLOG];
+    __shared__ cx<R> TW[(1 << MAXLOG) / 2];
+    const int logm = a.logm, M = 1 << logm;
+    bool tw_loaded = false;
+    for (int ri = blockIdx.x; ri < a.nrows; ri += gridDim.x) {
+        const RowRef rr = a.rows[ri];
+        const HilbertProb hp = a.hp[rr.prob];
+        if (!tw_loaded) {
+            const cx<R> *tg = (const cx<R> *)hp.tw_tab;
+            for (int k = threadIdx.x; k < M / 2; k += NT)
+                TW[k] = tg[k];
+            tw_loaded = true;
+        }
+        const int t = hp.t;
+        const cx<R> *ch = (const cx<R> *)hp.chirp;
+        const cx<R> *bh = (const cx<R> *)hp.bhat;
+        for (int k = threadIdx.x; k < M; k += NT)
+            X[k] = cx<R>{0, 0};
+        __syncthreads();
+        for (int b = 0; b < hp.nbands; ++b) {
+            const BandBins bb = a.bins[hp.bin0 + b];
+            auto weight = [&](int k) -> R {
+                if (bb.klo < 0)
+                    return k == 0 ? (R)1 : (2 * k < t ? (R)2 : (2 * k == t ? (R)1 : (R)0));
+                return (k >= bb.klo && k <= bb.khi) ? (R)2 : (R)0;
+            };
+            const GramDesc g = a.gd[hp.gram0 + b];
+            const cx<R> *zb = (const cx<R> *)g.zbuf + (int64_t)rr.row * g.ldz;
+            auto v_at = [&](int n) -> cx<R> {  // zbar on the full row, 0 off the window
+                const int s = n - hp.t0;
+                return (s >= 0 && s < hp.tw) ? zb[s] : cx<R>{0, 0};
+            };
+            if (!hp.blue) {
+                for (int n = threadIdx.x; n < M; n += NT)
+                    W[brev(n, logm)] = v_at(n);
+                __syncthreads();
+                fft_dit(W, TW, logm);
+                for (int k = threadIdx.x; k < M; k += NT)
+                    X[k] = cadd(X[k], cscale(W[k], weight(k)));
+            } else {
+                for (int n = threadIdx.x; n < M; n += NT) {
+                    cx<R> v{0, 0};
+                    if (n < t)
+                        v = cmul(v_at(n), cconj(ch[n]));
+                    W[brev(n, logm)] = v;
+                }
+                __syncthreads();
+                fft_dit(W, TW, logm);
+                for (int k = threadIdx.x; k < M; k += NT)
+                    W[k] = cmul(W[k], bh[k]);
+                __syncthreads();
+                ifft_dif(W, TW, logm);
+                const R invm = (R)1 / (R)M;
+                for (int k = threadIdx.x; k < t; k += NT)
+                    X[k] = cadd(X[k], cscale(cmul(cconj(ch[k]), W[brev(k, logm)]), weight(k) * invm));
+            }
+            __syncthreads();
+        }
+        // x_bar = Re(IDFT_t(X))
+        R *xb = (R *)hp.xbar + (int64_t)rr.row * hp.ld;
+        if (!hp.blue) {
+            for (int k = threadIdx.x; k < M; k += NT)
+                W[k] = X[k];
+            __syncthreads();
+            ifft_dif(W, TW, logm);
+            const R inv_t = (R)1 / (R)t;
+            for (int n = threadIdx.x; n < t; n += NT)
+                xb[n] = W[brev(n, logm)].x * inv_t;
+        } else {
+            // IDFT(X) = conj(DFT(conj X)) / t; only its real part is needed
+            for (int n = threadIdx.x; n < M; n += NT) {
+                cx<R> v{0, 0};
+                if (n < t)
+                    v = cconj(cmul(X[n], ch[n]));
+                W[brev(n, logm)] = v;
+            }
+            __syncthreads();
+            fft_dit(W, TW, logm);
+            for (int k = threadIdx.x; k < M; k += NT)
+                W[k] = cmul(W[k], bh[k]);
+            __syncthreads();
+            ifft_dif(W, TW, logm);
+            const R scale = (R)1 / ((R)M * (R)t);
+            for (int n = threadIdx.x; n < t; n += NT)
+                xb[n] = cmul(cconj(ch[n]), W[brev(n, logm)]).x * scale;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
+
+hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int nwg, hipStream_t s)
+{
+    if (nwg <= 0 || a.nrows <= 0)
+        return hipSuccess;
+    if (f64)
+        hilbert_adjoint_kernel<double, FFT_MAXLOG_F64><<<nwg, NT, 0, s>>>(a);
+    else
+        hilbert_adjoint_kernel<float, FFT_MAXLOG_F32><<<nwg, NT, 0, s>>>(a);
+    return hipGetLastError();
+}
 
 hipError_t launch_twiddles(bool f64, void *tab, int logm, hipStream_t s)
 {

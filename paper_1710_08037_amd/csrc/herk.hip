@@ -166,7 +166,7 @@ __device__ inline void herk_tile(const GramDesc &d, int I, int J, int k0, int ns
     const int lr = lane >> 2;
     const uint32_t voff = (uint32_t)(lr * pitch) + (uint32_t)(((lane & 3) ^ swz(lr)) * 16);
     const uint8_t *gA = d.u + (int64_t)I * BM * pitch + (int64_t)k0 * CB;
-    const uint8_t *gB = d.u + (int64_t)J * BM * pitch + (int64_t)k0 * CB;
+    const uint8_t *gB = (d.ub ? d.ub : d.u) + (int64_t)J * BM * pitch + (int64_t)k0 * CB;
     auto issue = [&](int st, int buf) {
         const int64_t koff = (int64_t)st * RB;
         uint8_t *base = smem + buf * STAGE;
@@ -355,7 +355,12 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
     }
     const int chunk = args.pass * d.nslot + slot;
     int I, J;
-    tile_ij(tile, d.ntile, I, J);
+    if (d.ub) {  // general product: full grid, row-major over (I, J)
+        I = tile / d.ntile_b;
+        J = tile - I * d.ntile_b;
+    } else {
+        tile_ij(tile, d.ntile, I, J);
+    }
     const int k0 = chunk * d.chunk;
     const int k1 = min(k0 + d.chunk, d.tpad);
     const int nst = (k1 - k0) / (RB / cbytes_of(MODE));
@@ -368,7 +373,7 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
             re[a][b] = acc_t{0, 0, 0, 0};
             im[a][b] = acc_t{0, 0, 0, 0};
         }
-    if (I == J)
+    if (I == J && !d.ub)
         herk_tile<MODE, true>(d, I, J, k0, nst, re, im, smem);
     else
         herk_tile<MODE, false>(d, I, J, k0, nst, re, im, smem);
@@ -378,6 +383,30 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
     if (wave >= 4)
         return;
     const int wm = wave >> 1, wn = wave & 1;
+    if (d.ub) {
+        // ---- general product: store the complex tile of C directly
+        typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
+        auto cp = gptr((cplx_t *)d.c);
+        const int rr0 = wm * (BM / 2) + (MODE == M_F64 ? (lane >> 4) : (lane >> 4) * 4);
+        constexpr int RS = (MODE == M_F64) ? 4 : 1;
+        const int cc0 = wn * (BM / 2) + (lane & 15);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = (int64_t)I * BM + rr0 + a * 16 + r * RS;
+                    const int64_t j = (int64_t)J * BM + cc0 + b * 16;
+                    if (i < d.n && j < d.nb) {
+                        cplx_t v;
+                        v.x = re[a][b][r];
+                        v.y = im[a][b][r];
+                        cp[i * d.ldc + j] = v;
+                    }
+                }
+        return;
+    }
     // ---- chunk sum of this tile -> partial[slot][tile][re|im][BM][BM] (FP64).
     // A chunk spans at most a few thousand samples, which bounds the FP32
     // accumulation error; later passes over a long T add into the same slot.

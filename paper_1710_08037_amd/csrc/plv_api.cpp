@@ -493,24 +493,225 @@ plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, 
     return enqueue_forward(ctx, plan, probs, bands, bands ? nbands : 1, fs, (uint8_t *)ws, (hipStream_t)stream);
 }
 
+// Backward: recompute the phasors (and, for real input, the analytic signal),
+// form H from the forward G and the upstream gradients, ubar = H U on MFMA,
+// then the normalisation adjoint and, for real input, the analytic-signal
+// adjoint.  Upstream gradients and G are [nbands][n][n] per problem.
+static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_problem *probs, const plv_grad *grads,
+                                   const plv_band *bands, int nbands, double fs, uint8_t *ws, hipStream_t s)
+{
+    const int mode = plan.mode;
+    const bool real = plan.op == PLV_OP_BACKWARD_REAL;
+    const bool f64 = mode == M_F64;
+    const size_t esz = f64 ? 8 : 4;  // output / gradient element
+    std::vector<GramDesc> gd;
+    fill_descs(plan, ws, gd);
+    std::vector<Item> items;
+    std::vector<TileRef> tiles;
+    if (plan.grouped)
+        build_tables(plan, gd, items, tiles);
+
+    std::vector<int> class_start, class_count;
+    {
+        std::vector<uint8_t> blob(plan.tables_bytes, 0);
+        memcpy(blob.data() + plan.desc_off, gd.data(), gd.size() * sizeof(GramDesc));
+        if (plan.grouped)
+            memcpy(blob.data() + plan.item_off, items.data(), items.size() * sizeof(Item));
+        if (real) {
+            const size_t nprob = plan.fft.size();
+            HilbertProb *hp = (HilbertProb *)(blob.data() + plan.hp_off);
+            BandBins *bins = (BandBins *)(blob.data() + plan.bin_off);
+            RowRef *rows = (RowRef *)(blob.data() + plan.row_off);
+            ChirpJob *jobs = (ChirpJob *)(blob.data() + plan.job_off);
+            for (size_t q = 0; q < nprob; ++q) {
+                const FftPlan &f = plan.fft[q];
+                const plv_problem &p = probs[q];
+                HilbertProb h{};
+                h.x = p.in;
+                h.ld = p.ld;
+                h.n = (int32_t)p.n;
+                h.t = f.t;
+                h.t0 = (int32_t)p.t0;
+                h.tw = plan.grams[q * nbands].t;
+                h.logm = f.logm;
+                h.blue = f.blue ? 1 : 0;
+                h.chirp = f.blue ? ws + plan.chirp_off[f.chirp_index] : nullptr;
+                h.bhat = f.blue ? ws + plan.bhat_off[f.chirp_index] : nullptr;
+                h.tw_tab = ws + plan.tw_off[f.tw_index];
+                h.gram0 = (int32_t)(q * nbands);
+                h.nbands = nbands;
+                h.bin0 = (int32_t)(q * nbands);
+                h.xbar = grads[q].din;
+                hp[q] = h;
+                for (int b = 0; b < nbands; ++b)
+                    bins[q * nbands + b] = band_bins(f.t, fs, bands ? &bands[b] : nullptr);
+            }
+            size_t r = 0;
+            for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+                class_start.push_back((int)r);
+                for (size_t q = 0; q < nprob; ++q)
+                    if (plan.fft[q].logm == plan.tw_logm[c])
+                        for (int64_t i = 0; i < probs[q].n; ++i)
+                            rows[r++] = RowRef{(int32_t)q, (int32_t)i};
+                class_count.push_back((int)r - class_start.back());
+            }
+            for (size_t c = 0; c < plan.chirp_t.size(); ++c)
+                jobs[c] = ChirpJob{plan.chirp_t[c], plan.chirp_logm[c], ws + plan.chirp_off[c], ws + plan.bhat_off[c]};
+        }
+        plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
+        if (st != PLV_OK)
+            return st;
+    }
+
+    StageTimer tm(ctx, PLV_STAGE_BACKWARD, s);
+    hipError_t e;
+    HilbertArgs ha{};
+    ha.hp = (const HilbertProb *)(ws + plan.hp_off);
+    ha.bins = (const BandBins *)(ws + plan.bin_off);
+    ha.gd = (const GramDesc *)(ws + plan.desc_off);
+    if (real) {
+        // analytic signal of the window, kept unnormalised in zbuf
+        for (size_t c = 0; c < plan.tw_logm.size(); ++c)
+            if ((e = launch_twiddles(f64, ws + plan.tw_off[c], plan.tw_logm[c], s)) != hipSuccess)
+                return hip_fail(ctx, e, "twiddle kernel launch");
+        if (!plan.chirp_t.empty() &&
+            (e = launch_chirps(f64, (const ChirpJob *)(ws + plan.job_off), (int)plan.chirp_t.size(), s)) != hipSuccess)
+            return hip_fail(ctx, e, "chirp kernel launch");
+        for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+            ha.rows = (const RowRef *)(ws + plan.row_off) + class_start[c];
+            ha.nrows = class_count[c];
+            ha.logm = plan.tw_logm[c];
+            if ((e = launch_hilbert(mode, ha, std::min(class_count[c], ctx->cus), s)) != hipSuccess)
+                return hip_fail(ctx, e, "analytic-signal kernel launch");
+        }
+        tm.launched(3);
+    }
+    // operands of ubar = H (conj U^T)^H
+    for (size_t q = 0; q < plan.grams.size(); ++q) {
+        const GramPlan &g = plan.grams[q];
+        const plv_problem &p = probs[g.prob];
+        const plv_grad &gr = grads[g.prob];
+        BwdPlanesArgs pa{};
+        if (real) {
+            pa.z = ws + g.z_off;
+            pa.ldz = g.t;
+        } else {
+            pa.z = (const uint8_t *)p.in + (size_t)g.t0 * 2 * esz;
+            pa.ldz = p.ld;
+        }
+        pa.n = g.n;
+        pa.tw = g.t;
+        pa.kpad = g.kpad;
+        pa.w = ws + g.w_off;
+        pa.plane_bytes = (int64_t)g.plane_bytes;
+        if ((e = launch_planes_t(mode, pa, s)) != hipSuccess)
+            return hip_fail(ctx, e, "transposed phasor kernel launch");
+        const size_t ob = (size_t)g.band * g.n * g.n * esz;
+        BwdMetricArgs ma{};
+        ma.g = (const uint8_t *)p.g + 2 * ob;
+        ma.dplv = gr.dplv ? (const uint8_t *)gr.dplv + ob : nullptr;
+        ma.diplv = gr.diplv ? (const uint8_t *)gr.diplv + ob : nullptr;
+        ma.dciplv = gr.dciplv ? (const uint8_t *)gr.dciplv + ob : nullptr;
+        ma.n = g.n;
+        ma.kpad = g.kpad;
+        ma.inv_t = 1.0 / (double)g.t;
+        ma.h = ws + g.u_off;
+        ma.plane_bytes = (int64_t)g.plane_bytes;
+        if ((e = launch_metric_adjoint(mode, ma, s)) != hipSuccess)
+            return hip_fail(ctx, e, "metric adjoint kernel launch");
+        tm.launched(2);
+    }
+    // ubar on MFMA
+    if (!plan.grouped) {
+        HerkArgs hk{};
+        hk.g = gd[0];
+        if ((e = launch_herk(mode, hk, gd[0].nupper, s)) != hipSuccess)
+            return hip_fail(ctx, e, "product kernel launch");
+    } else {
+        HerkArgs hk{};
+        hk.gd = (const GramDesc *)(ws + plan.desc_off);
+        hk.items = (const Item *)(ws + plan.item_off);
+        hk.nitems = (int32_t)items.size();
+        if ((e = launch_herk(mode, hk, (int)items.size(), s)) != hipSuccess)
+            return hip_fail(ctx, e, "product kernel launch");
+    }
+    tm.launched();
+    // through the normalisation
+    for (size_t q = 0; q < plan.grams.size(); ++q) {
+        const GramPlan &g = plan.grams[q];
+        const plv_problem &p = probs[g.prob];
+        BwdNormArgs na{};
+        na.c = ws + g.c_off;
+        na.ldc = g.t;
+        na.tw = g.t;
+        na.n = g.n;
+        if (real) {
+            na.z = ws + g.z_off;  // zbar replaces z in place
+            na.ldz = g.t;
+            na.dst = ws + g.z_off;
+            na.ldd = g.t;
+            na.off = 0;
+            na.len = g.t;
+        } else {
+            na.z = (const uint8_t *)p.in + (size_t)g.t0 * 2 * esz;
+            na.ldz = p.ld;
+            na.dst = grads[g.prob].din;
+            na.ldd = p.ld;
+            na.off = g.t0;
+            na.len = (int32_t)p.t;
+        }
+        if ((e = launch_normalise_adjoint(f64, na, s)) != hipSuccess)
+            return hip_fail(ctx, e, "normalisation adjoint kernel launch");
+        tm.launched();
+    }
+    // through the analytic signal
+    if (real) {
+        for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+            ha.rows = (const RowRef *)(ws + plan.row_off) + class_start[c];
+            ha.nrows = class_count[c];
+            ha.logm = plan.tw_logm[c];
+            if ((e = launch_hilbert_adjoint(f64, ha, std::min(class_count[c], ctx->cus), s)) != hipSuccess)
+                return hip_fail(ctx, e, "analytic-signal adjoint kernel launch");
+            tm.launched();
+        }
+    }
+    return PLV_OK;
+}
+
 plv_status plv_backward(plv_ctx *ctx, plv_prec prec, plv_input kind, const plv_problem *probs,
                         const plv_grad *grads, int64_t nprob, const plv_band *bands, int32_t nbands, double fs,
                         void *ws, size_t ws_bytes, void *stream)
 {
-    (void)prec;
-    (void)kind;
-    (void)probs;
-    (void)grads;
-    (void)nprob;
-    (void)bands;
-    (void)nbands;
-    (void)fs;
-    (void)ws;
-    (void)ws_bytes;
-    (void)stream;
     if (!ctx)
         return PLV_ERR_INVALID_ARG;
-    return fail(ctx, PLV_ERR_UNSUPPORTED, "plv_backward: not built yet");
+    if (kind != PLV_INPUT_ANALYTIC && kind != PLV_INPUT_REAL)
+        return fail(ctx, PLV_ERR_INVALID_ARG, "unknown input kind");
+    if (!grads)
+        return fail(ctx, PLV_ERR_INVALID_ARG, "grads is NULL");
+    const bool real = kind == PLV_INPUT_REAL;
+    if (real && bands) {
+        for (int32_t b = 0; b < nbands; ++b)
+            if ((bands[b].f_lo != 0.0 || bands[b].f_hi != 0.0) && !(fs > 0.0 && std::isfinite(fs)))
+                return fail(ctx, PLV_ERR_INVALID_ARG, "a band-pass band needs a finite sampling rate fs > 0");
+    }
+    Plan plan;
+    const plv_op op = real ? PLV_OP_BACKWARD_REAL : PLV_OP_BACKWARD_ANALYTIC;
+    plv_status st = begin(ctx, op, prec, probs, nprob, real ? bands : nullptr, real ? nbands : 1, ws, ws_bytes, plan);
+    if (st != PLV_OK)
+        return st;
+    const size_t esz = plan.mode == M_F64 ? 8 : 4;
+    for (int64_t q = 0; q < nprob; ++q) {
+        if (!grads[q].din)
+            return fail(ctx, PLV_ERR_INVALID_ARG, "problem %lld: din is NULL", (long long)q);
+        const void *gp[3] = {grads[q].dplv, grads[q].diplv, grads[q].dciplv};
+        for (int k = 0; k < 3; ++k)
+            if (gp[k] && reinterpret_cast<uintptr_t>(gp[k]) % esz)
+                return fail(ctx, PLV_ERR_INVALID_ARG, "problem %lld: upstream gradients misaligned", (long long)q);
+        if (reinterpret_cast<uintptr_t>(grads[q].din) % (real ? esz : 2 * esz > 16 ? 16 : 2 * esz))
+            return fail(ctx, PLV_ERR_INVALID_ARG, "problem %lld: din misaligned", (long long)q);
+    }
+    return enqueue_backward(ctx, plan, probs, grads, real ? bands : nullptr, real ? (bands ? nbands : 1) : 1, fs,
+                            (uint8_t *)ws, (hipStream_t)stream);
 }
 
 }  // extern "C"

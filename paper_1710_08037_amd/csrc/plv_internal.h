@@ -64,6 +64,15 @@ struct GramDesc {
     int32_t pad_;
     double *partial;      // [nslot][nupper][2][BM][BM] FP64 chunk sums
     void *plv, *iplv, *ciplv, *g;  // outputs, [n][n] (g complex interleaved)
+    // General product mode (used by the backward): C = A B^H over the full
+    // tile grid, A = the planes at u (rows n), B = the planes at ub (rows nb),
+    // same row pitch; C stored directly as complex (f32; f64 in F64 mode).
+    const uint8_t *ub;    // B operand planes, nullptr in Gram mode
+    int32_t nb, ntile_b;  // B rows, B tiles
+    void *c;              // C [n][ldc] complex
+    int64_t ldc;
+    void *zbuf;           // FFT stage of the backward: complex z of the window
+    int64_t ldz;          //   [n][ldz] written instead of phasor planes
 };
 
 // One unit of Gram work: a (problem, tile, chunk) triple.
@@ -119,6 +128,7 @@ struct HilbertProb {
     int32_t nbands;
     int32_t bin0;        // first entry of this problem in the band-bin table
     int32_t pad_;
+    void *xbar;          // backward: dL/dx rows [n][ld] (same dtype as x)
 };
 
 // Positive-frequency bins [klo, khi] that get weight 2; klo < 0 selects the
@@ -147,6 +157,34 @@ struct ChirpJob {
     void *bhat;           // [M] complex (written as the circular chirp, then transformed in place)
 };
 
+// ---------------------------------------------------------------- backward --
+struct BwdPlanesArgs {      // W[s][k] = conj(u_k(s)): the product's B operand
+    const void *z;           // complex rows of the window [n][ldz]
+    int64_t ldz;
+    int32_t n, tw, kpad;
+    uint8_t *w;              // planes [rows >= tw][kpad]
+    int64_t plane_bytes;
+};
+
+struct BwdMetricArgs {      // H = (Gbar + Gbar^H) / T: the product's A operand
+    const void *g;           // forward complex G [n][n]
+    const void *dplv, *diplv, *dciplv;  // upstream [n][n] (nullptr = 0)
+    int32_t n, kpad;
+    double inv_t;
+    uint8_t *h;              // planes [npad][kpad]
+    int64_t plane_bytes;
+};
+
+struct BwdNormArgs {        // zbar = i Im(conj(u) ubar) u / |z|
+    const void *z;           // window rows [n][ldz]
+    int64_t ldz;
+    const void *c;           // ubar rows [n][ldc]
+    int64_t ldc;
+    void *dst;               // output rows [n][ldd]; sample s of the window at q = s + off
+    int64_t ldd;
+    int32_t off, len, tw, n; // q runs over [0, len); outside the window -> 0
+};
+
 // -------------------------------------------------------------- launchers --
 // Each returns hipSuccess or the launch error.
 hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s);
@@ -160,5 +198,9 @@ constexpr int FFT_MAXLOG_F64 = 12;  // M <= 4096 complex FP64
 hipError_t launch_twiddles(bool f64, void *tab, int logm, hipStream_t s);
 hipError_t launch_chirps(bool f64, const ChirpJob *jobs, int njobs, hipStream_t s);
 hipError_t launch_hilbert(int mode, const HilbertArgs &a, int nwg, hipStream_t s);
+hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int nwg, hipStream_t s);
+hipError_t launch_planes_t(int mode, const BwdPlanesArgs &a, hipStream_t s);
+hipError_t launch_metric_adjoint(int mode, const BwdMetricArgs &a, hipStream_t s);
+hipError_t launch_normalise_adjoint(bool f64, const BwdNormArgs &a, hipStream_t s);
 
 }  // namespace plv

@@ -167,6 +167,12 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         }
     }
 
+    const bool backward = (op == PLV_OP_BACKWARD_ANALYTIC || op == PLV_OP_BACKWARD_REAL);
+    if (backward && (mode == M_BF16 || mode == M_F16)) {
+        // the backward operand H is unbounded: plain 16-bit phasors are not
+        // accurate enough for it, so these modes run their adjoint in split form
+        plan.mode = M_SPLIT;
+    }
     const int slots = std::max(1, cus) * std::max(1, occ ? occ[mode] : 1);
     const bool grouped = plan.grams.size() > 1;
     plan.grouped = grouped;
@@ -176,7 +182,27 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
     plan.tables_off = 0;
     plan.desc_off = 0;
     off = align256(plan.grams.size() * sizeof(GramDesc));
-    if (grouped) {
+    if (backward) {
+        // general product tiles: rows of H x rows of W, one K-chunk (K = n)
+        for (GramPlan &g : plan.grams) {
+            g.kpad = (g.n + PLV_KGRAN - 1) / PLV_KGRAN * PLV_KGRAN;
+            g.ntile_b = (g.t + bm - 1) / bm;
+            g.nupper = g.ntile * g.ntile_b;
+            g.chunk = g.kpad;
+            g.nchunk = 1;
+            g.nslot = 1;
+        }
+        if (grouped) {
+            for (const GramPlan &g : plan.grams)
+                plan.nitems += (size_t)g.nupper;
+            if (plan.nitems > (size_t)INT32_MAX) {
+                why = "too many work items";
+                return PLV_ERR_INVALID_ARG;
+            }
+            plan.item_off = off;
+            off += align256(plan.nitems * sizeof(Item));
+        }
+    } else if (grouped) {
         for (GramPlan &g : plan.grams)
             choose_chunks_grouped(g);
         for (const GramPlan &g : plan.grams) {
@@ -247,6 +273,26 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
     } else {
         plan.tables_bytes = off;
     }
+    if (backward) {
+        const int bpl = planes_of(plan.mode), bcb = cbytes_of(plan.mode);
+        const size_t csz = mode == M_F64 ? 16 : 8;
+        for (GramPlan &g : plan.grams) {
+            const size_t rows = (size_t)std::max(g.npad, g.ntile_b * bm);
+            g.plane_bytes = align256(rows * g.kpad * bcb);
+            g.u_off = off;
+            off += g.plane_bytes * bpl;
+            g.w_off = off;
+            off += g.plane_bytes * bpl;
+            g.c_off = off;
+            off += align256((size_t)g.n * g.t * csz);
+            if (real) {
+                g.z_off = off;
+                off += align256((size_t)g.n * g.t * csz);
+            }
+        }
+        plan.total = off;
+        return PLV_OK;
+    }
     for (GramPlan &g : plan.grams) {
         g.plane_bytes = align256((size_t)g.npad * g.tpad * cb);
         g.u_off = off;
@@ -282,6 +328,20 @@ void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd)
         d.iplv = g.iplv;
         d.ciplv = g.ciplv;
         d.g = g.g;
+        if (plan.op == PLV_OP_BACKWARD_ANALYTIC || plan.op == PLV_OP_BACKWARD_REAL) {
+            d.ldu = g.kpad;
+            d.tpad = g.kpad;
+            d.ub = ws + g.w_off;
+            d.nb = g.t;
+            d.ntile_b = g.ntile_b;
+            d.c = ws + g.c_off;
+            d.ldc = g.t;
+            d.partial = nullptr;
+            if (plan.op == PLV_OP_BACKWARD_REAL) {
+                d.zbuf = ws + g.z_off;
+                d.ldz = g.t;
+            }
+        }
         gd.push_back(d);
     }
 }
@@ -293,13 +353,15 @@ void build_tables(const Plan &plan, const std::vector<GramDesc> &gd, std::vector
     tiles.clear();
     items.reserve(plan.nitems);
     tiles.reserve(plan.ntiles);
+    const bool backward = plan.op == PLV_OP_BACKWARD_ANALYTIC || plan.op == PLV_OP_BACKWARD_REAL;
     for (size_t q = 0; q < gd.size(); ++q) {
         const GramDesc &d = gd[q];
         for (int c = 0; c < d.nchunk; ++c)
             for (int t = 0; t < d.nupper; ++t)
                 items.push_back(Item{(int32_t)q, t, c, 0});
-        for (int t = 0; t < d.nupper; ++t)
-            tiles.push_back(TileRef{(int32_t)q, t});
+        if (!backward)
+            for (int t = 0; t < d.nupper; ++t)
+                tiles.push_back(TileRef{(int32_t)q, t});
     }
     // longest items first, so the tail of the launch is short work
     auto cost = [&](const Item &it) {

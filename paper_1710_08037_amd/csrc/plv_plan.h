@@ -22,8 +22,13 @@ struct GramPlan {
     int t = 0, t0 = 0, tpad = 0;       // window length, window start, padded length
     int ntile = 0, nupper = 0;
     int nchunk = 0, chunk = 0, nslot = 0;
-    size_t u_off = 0, plane_bytes = 0; // phasor planes
+    size_t u_off = 0, plane_bytes = 0; // phasor planes (backward: the H operand)
     size_t part_off = 0;               // FP64 partial sums
+    // backward only: C = H (conj U^T)^H over the full tile grid
+    int kpad = 0, ntile_b = 0;
+    size_t w_off = 0;                  // W = conj(U^T) planes (B operand)
+    size_t c_off = 0;                  // ubar [n][t] complex
+    size_t z_off = 0;                  // real input: z, then zbar, [n][t] complex
     void *plv = nullptr, *iplv = nullptr, *ciplv = nullptr, *g = nullptr;
 };
 

@@ -277,3 +277,23 @@ def test_gradient_upstream_is_symmetrised():
     a = oracle.grad_from_analytic(z, gp=w)
     b = oracle.grad_from_analytic(z, gp=np.triu(w + w.T, 1))
     assert np.abs(a - b).max() < 1e-14
+
+
+# ------------------------------------------------- large-size helper paths ---
+
+@pytest.mark.parametrize("t,band", [(64, None), (101, None), (1000, (8.0, 12.0))])
+def test_fft_analytic_equals_plain_dft_sums(t, band):
+    x = RNG.standard_normal((4, t))
+    a = oracle.analytic(x, 1000.0, band)
+    b = oracle.analytic_fft(x, 1000.0, band)
+    assert np.abs(a - b).max() < 1e-11
+
+
+def test_row_subset_gradient_equals_full_gradient():
+    n, t = 9, 40
+    x = synth.glag_real(n, t, 100.0, 3, 10.0, seed=43, noise_var=0.3)
+    w = [RNG.standard_normal((n, n)) for _ in range(3)]
+    full = oracle.grad_from_real(x, gp=w[0], gi=w[1], gc=w[2], window=(3, 37), nthreads=2)
+    rows = [0, 4, 8]
+    sub = oracle.grad_from_real_rows(x, rows, gp=w[0], gi=w[1], gc=w[2], window=(3, 37), nthreads=2)
+    assert np.abs(sub - full[rows]).max() < 1e-12 * max(1.0, np.abs(full).max())
