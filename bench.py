@@ -13,7 +13,14 @@ The plain FP32 path runs on the same input for comparison, and both are
 checked against the FP64 oracle on a sample of pairs (in the CPU-baseline
 leg, which also times the oracle).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+Other workloads (--workload; each prints its own JSON line, same
+conventions): ``small`` N = 64 real f64 signals, T = 2048 at 256 Hz, FP64
+end to end; ``batch`` 512 trials of uneven N in {68, 148, 360, 1000} and T in
+[500, 4000] at 1 kHz, five 4 Hz bands each, real f32, FFT analytic signal and
+one grouped Gram launch; ``grad`` N = 2048 real f32 signals, T = 8192,
+forward plus adjoint of the ciPLV target loss.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
@@ -138,6 +145,97 @@ def cpu_baseline(z_np, gpu_out, budget_s=15.0):
     return base, errs
 
 
+def timed(fn, steps, warmup):
+    """(ms per step, stage timings) of fn() on the current stream."""
+    import torch
+
+    import paper_1710_08037_amd as plv
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    plv.timing_enable(True)
+    plv.timing_read(reset=True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    stages = plv.timing_read(reset=True)
+    plv.timing_enable(False)
+    per = {k: round(v[0] / steps, 4) for k, v in stages.items() if v[1]}
+    return start.elapsed_time(stop) / steps, per
+
+
+def line_for(workload, value, ms, args, dtype, config, extra):
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "pair-samples/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": dict(workload=workload, **config)}
+    out.update(extra)
+    return out
+
+
+def bench_small(args):
+    import numpy as np
+    import torch
+
+    import paper_1710_08037_amd as plv
+    import synth
+
+    x = torch.from_numpy(synth.glag_real(64, 2048, 256.0, 8, 10.0, seed=synth.seed_for(1))).cuda()
+    ms, stages = timed(lambda: plv.from_real(x, 256.0, prec="f64"), args.steps, args.warmup)
+    ps = 64 * 63 // 2 * 2048
+    return line_for("small FP64: N=64 real f64 x T=2048 at 256 Hz, plain analytic signal", ps / (ms / 1e3), ms,
+                    args, "f64", {"n": 64, "t": 2048, "prec": "f64"}, {"stage_ms": stages})
+
+
+def bench_batch(args):
+    import numpy as np
+    import torch
+
+    import paper_1710_08037_amd as plv
+    import synth
+
+    seed = synth.seed_for(4)
+    shapes = synth.batch_shapes(512, seed)
+    xs = [torch.from_numpy(synth.glag_real(n, t, 1000.0, 32, (2.0, 42.0), seed=seed + 1 + k,
+                                           dtype=np.float32)).cuda() for k, (n, t) in enumerate(shapes)]
+    bands = synth.bands_hz()
+    ms, stages = timed(lambda: plv.from_real_batch(xs, 1000.0, bands=bands, prec=args.prec_batch), args.steps,
+                       args.warmup)
+    ps = sum(n * (n - 1) // 2 * t for n, t in shapes) * len(bands)
+    return line_for("uneven batch: 512 trials, N in {68,148,360,1000}, T in [500,4000], 5 bands, real f32",
+                    ps / (ms / 1e3), ms, args, "bf16", {"trials": 512, "bands": len(bands),
+                                                        "prec": args.prec_batch},
+                    {"stage_ms": stages, "pair_samples": ps, "rows": sum(n for n, _ in shapes)})
+
+
+def bench_grad(args):
+    import numpy as np
+    import torch
+
+    import paper_1710_08037_amd as plv
+    import synth
+
+    n, t, fs = 2048, 8192, 1000.0
+    x = torch.from_numpy(synth.glag_real(n, t, fs, 32, (8.0, 12.0), seed=synth.seed_for(5),
+                                         dtype=np.float32)).cuda()
+    cstar = torch.from_numpy(synth.sparse_target(n, seed=synth.seed_for(5, 1))).float().cuda()
+    upper = torch.triu(torch.ones(n, n, device="cuda"), 1)
+
+    def step():
+        out = plv.from_real(x, fs, prec=args.prec_batch, want_g=True, want=("ciplv",))
+        dc = (2 * (out["ciplv"][0] - cstar) * upper)[None]
+        return plv.backward_batch([x], [out["g"]], [(None, None, dc)], fs=fs, prec=args.prec_batch)[0]
+
+    ms, stages = timed(step, args.steps, args.warmup)
+    ps = n * (n - 1) // 2 * t
+    return line_for("differentiable ciPLV: N=2048 real f32 x T=8192, forward + adjoint", ps / (ms / 1e3), ms,
+                    args, "bf16", {"n": n, "t": t, "prec": args.prec_batch}, {"stage_ms": stages})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +246,8 @@ def main():
                     help="paths to time (both: split-BF16 for `value`, FP32 beside it)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 3 times (counter calibration) and exit")
+    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad"])
+    ap.add_argument("--prec-batch", default="split_bf16", help="precision of the batch and grad workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X (use --gpus 1)", file=sys.stderr)
@@ -166,6 +266,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_ref_bytes": args.copy_ref}), flush=True)
+        return
+    if args.workload != "sensor":
+        fn = {"small": bench_small, "batch": bench_batch, "grad": bench_grad}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
         return
     z_np = synth.glag_analytic(N_SIG, T_SAMP, FS, 32, (8.0, 12.0), seed=synth.seed_for(2), dtype=np.complex64)
     z = torch.from_numpy(z_np).cuda()

@@ -1,19 +1,16 @@
-// epilogue.hip -- chunk sum + metrics + mirrored store.
+// epilogue.hip -- chunk sum + metrics + mirrored store for problems whose T
+// spans several K-chunks (single-chunk problems get the same store fused into
+// the Gram kernel).
 //
 // For each upper-triangle tile: G_ij = (1/T) sum_s partial_s(i, j), the slots
 // added in index order in FP64 (deterministic; no float atomics), T the true
-// window length.  Then
-//   PLV = |G|                               (Eq. 2 / Eq. 7)
-//   iPLV = |Im G|                           (Section II.C, Eq. 13)
-//   ciPLV = |Im G| / sqrt((1-Re)(1+Re))     (Eq. 14; FP64 radicand, 0 if <= 0)
-// written at (i, j) and (j, i); the diagonal gets PLV = 1, iPLV = ciPLV = 0
-// and the computed G_ii.  G is written as G_ij and G_ji = conj(G_ij), so every
-// output is exactly symmetric (Hermitian for G).
+// window length; then the measures of Eqs. 2, 13 and 14 at (i, j) and (j, i)
+// (metrics.h).
 //
 // Each work-group covers 1024 elements (8 rows) of one tile so that even a
 // small problem spreads over many CUs; reads of the partial sums are
 // contiguous along j.
-#include "plv_internal.h"
+#include "metrics.h"
 
 namespace plv {
 namespace {
@@ -22,8 +19,6 @@ template <int MODE>
 __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
 {
     constexpr int BM = tile_of(MODE);
-    typedef typename std::conditional<MODE == M_F64, double, float>::type real_t;
-    typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
 
     GramDesc d;
     int tile;
@@ -46,8 +41,6 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
     const int64_t cstride = (int64_t)d.nupper * 2 * BM * BM;
     const double inv_t = 1.0 / (double)d.t;
     const int64_t n = d.n;
-    auto plv = gptr((real_t *)d.plv), iplv = gptr((real_t *)d.iplv), ciplv = gptr((real_t *)d.ciplv);
-    auto g = gptr((cplx_t *)d.g);
 
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -61,45 +54,7 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
             sr += part[c * cstride + e];
             si += part[c * cstride + BM * BM + e];
         }
-        const double r = sr * inv_t, m = si * inv_t;
-        const int64_t ij = gi * n + gj, ji = gj * n + gi;
-        if (gi == gj) {
-            if (plv) plv[ij] = (real_t)1;
-            if (iplv) iplv[ij] = (real_t)0;
-            if (ciplv) ciplv[ij] = (real_t)0;
-            if (g) {
-                cplx_t v;
-                v.x = (real_t)r;
-                v.y = (real_t)m;
-                g[ij] = v;
-            }
-            continue;
-        }
-        const double am = fabs(m);
-        const double dd = (1.0 - r) * (1.0 + r);
-        const real_t vp = (real_t)sqrt(r * r + m * m);
-        const real_t vi = (real_t)am;
-        const real_t vc = (real_t)(dd > 0.0 ? am / sqrt(dd) : 0.0);
-        if (plv) {
-            plv[ij] = vp;
-            plv[ji] = vp;
-        }
-        if (iplv) {
-            iplv[ij] = vi;
-            iplv[ji] = vi;
-        }
-        if (ciplv) {
-            ciplv[ij] = vc;
-            ciplv[ji] = vc;
-        }
-        if (g) {
-            cplx_t v;
-            v.x = (real_t)r;
-            v.y = (real_t)m;
-            g[ij] = v;
-            v.y = (real_t)(-m);
-            g[ji] = v;
-        }
+        store_entry<MODE>(d, gi, gj, sr * inv_t, si * inv_t);
     }
 }
 

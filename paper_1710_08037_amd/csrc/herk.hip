@@ -5,8 +5,10 @@
 // (Re, Im as two BM x BM FP64 planes) to a slot of the partial buffer; the
 // epilogue kernel adds the slots in a fixed order.  When T has more chunks
 // than slots, the host launches several passes and pass p > 0 adds chunk
-// p * nslot + s into slot s.  Only the upper triangle is computed:
-// G_ji = conj(G_ij).
+// p * nslot + s into slot s.  A problem whose T is a single chunk skips the
+// partial buffer: the work-group divides by T and stores PLV, iPLV, ciPLV
+// (and G) itself, with the same FP64 arithmetic as the epilogue.  Only the
+// upper triangle is computed: G_ji = conj(G_ij).
 //
 // Complex arithmetic on real MFMA.  Per sample the phasor is stored
 // interleaved, p(t) = (Re u, Im u).  With q(t) = (Im u, -Re u):
@@ -31,7 +33,7 @@
 // round-robin over the 8 XCDs, so ids are remapped to give each XCD a
 // contiguous range of items (same chunk, neighbouring tiles), which keeps the
 // shared row panels in that XCD's L2.
-#include "plv_internal.h"
+#include "metrics.h"
 
 namespace plv {
 namespace {
@@ -404,6 +406,25 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
                         v.y = im[a][b][r];
                         cp[i * d.ldc + j] = v;
                     }
+                }
+        return;
+    }
+    if (d.fused) {
+        // ---- single chunk: the measures straight from the accumulators
+        const double inv_t = 1.0 / (double)d.t;
+        const int r0 = wm * (BM / 2) + (MODE == M_F64 ? (lane >> 4) : (lane >> 4) * 4);
+        constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;
+        const int c0 = wn * (BM / 2) + (lane & 15);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t gi = (int64_t)I * BM + r0 + a * 16 + r * RSTEP;
+                    const int64_t gj = (int64_t)J * BM + c0 + b * 16;
+                    if (gi < d.n && gj < d.n && gi <= gj)
+                        store_entry<MODE>(d, gi, gj, (double)re[a][b][r] * inv_t, (double)im[a][b][r] * inv_t);
                 }
         return;
     }

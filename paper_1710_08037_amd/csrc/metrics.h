@@ -1,0 +1,74 @@
+// metrics.h -- the three phase-synchrony measures of one entry of G and their
+// symmetric store.  Shared by the epilogue kernel (multi-chunk problems) and
+// the Gram kernel's fused store (single-chunk problems), so both write
+// bit-identical results.
+//
+//   PLV   = |G|                             (Eq. 2 / Eq. 7)
+//   iPLV  = |Im G|                          (Section II.C, Eq. 13)
+//   ciPLV = |Im G| / sqrt((1-Re)(1+Re))     (Eq. 14; FP64 radicand, 0 if <= 0)
+//
+// written at (i, j) and (j, i); the diagonal gets PLV = 1, iPLV = ciPLV = 0
+// and the computed G_ii.  G is written as G_ij and G_ji = conj(G_ij), so every
+// output is exactly symmetric (Hermitian for G).
+#pragma once
+
+#include "plv_internal.h"
+
+namespace plv {
+
+template <int MODE>
+struct OutT {
+    typedef typename std::conditional<MODE == M_F64, double, float>::type real_t;
+    typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
+};
+
+// r, m: Re and Im of G_ij (already divided by T); gi <= gj < d.n.
+template <int MODE>
+__device__ inline void store_entry(const GramDesc &d, int64_t gi, int64_t gj, double r, double m)
+{
+    typedef typename OutT<MODE>::real_t real_t;
+    typedef typename OutT<MODE>::cplx_t cplx_t;
+    auto plv = gptr((real_t *)d.plv), iplv = gptr((real_t *)d.iplv), ciplv = gptr((real_t *)d.ciplv);
+    auto g = gptr((cplx_t *)d.g);
+    const int64_t n = d.n;
+    const int64_t ij = gi * n + gj, ji = gj * n + gi;
+    if (gi == gj) {
+        if (plv) plv[ij] = (real_t)1;
+        if (iplv) iplv[ij] = (real_t)0;
+        if (ciplv) ciplv[ij] = (real_t)0;
+        if (g) {
+            cplx_t v;
+            v.x = (real_t)r;
+            v.y = (real_t)m;
+            g[ij] = v;
+        }
+        return;
+    }
+    const double am = fabs(m);
+    const double dd = (1.0 - r) * (1.0 + r);
+    const real_t vp = (real_t)sqrt(r * r + m * m);
+    const real_t vi = (real_t)am;
+    const real_t vc = (real_t)(dd > 0.0 ? am / sqrt(dd) : 0.0);
+    if (plv) {
+        plv[ij] = vp;
+        plv[ji] = vp;
+    }
+    if (iplv) {
+        iplv[ij] = vi;
+        iplv[ji] = vi;
+    }
+    if (ciplv) {
+        ciplv[ij] = vc;
+        ciplv[ji] = vc;
+    }
+    if (g) {
+        cplx_t v;
+        v.x = (real_t)r;
+        v.y = (real_t)m;
+        g[ij] = v;
+        v.y = (real_t)(-m);
+        g[ji] = v;
+    }
+}
+
+}  // namespace plv

@@ -438,6 +438,8 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
                 tm.launched();
             }
         }
+        if (d.fused)
+            return PLV_OK;
         StageTimer tm(ctx, PLV_STAGE_EPILOGUE, s);
         EpiArgs ea{};
         ea.g = d;
@@ -456,6 +458,8 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             return hip_fail(ctx, e, "gram kernel launch");
         tm.launched();
     }
+    if (tiles.empty())
+        return PLV_OK;
     StageTimer tm(ctx, PLV_STAGE_EPILOGUE, s);
     EpiArgs ea{};
     ea.gd = ha.gd;

@@ -61,8 +61,8 @@ struct GramDesc {
     int32_t nchunk;       // K-chunks over tpad
     int32_t chunk;        // samples per chunk (multiple of PLV_KGRAN); last may be shorter
     int32_t nslot;        // partial slots (chunks per pass); passes = ceil(nchunk / nslot)
-    int32_t pad_;
-    double *partial;      // [nslot][nupper][2][BM][BM] FP64 chunk sums
+    int32_t fused;        // 1: one chunk, the Gram kernel stores the measures itself
+    double *partial;      // [nslot][nupper][2][BM][BM] FP64 chunk sums (unused when fused)
     void *plv, *iplv, *ciplv, *g;  // outputs, [n][n] (g complex interleaved)
     // General product mode (used by the backward): C = A B^H over the full
     // tile grid, A = the planes at u (rows n), B = the planes at ub (rows nb),

@@ -203,11 +203,14 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
             off += align256(plan.nitems * sizeof(Item));
         }
     } else if (grouped) {
-        for (GramPlan &g : plan.grams)
+        for (GramPlan &g : plan.grams) {
             choose_chunks_grouped(g);
+            g.fused = g.nchunk == 1;
+        }
         for (const GramPlan &g : plan.grams) {
             plan.nitems += (size_t)g.nupper * g.nchunk;
-            plan.ntiles += (size_t)g.nupper;
+            if (!g.fused)
+                plan.ntiles += (size_t)g.nupper;
         }
         if (plan.nitems > (size_t)INT32_MAX || plan.ntiles > (size_t)INT32_MAX) {
             why = "too many work items";
@@ -219,6 +222,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         off += align256(plan.ntiles * sizeof(TileRef));
     } else {
         choose_chunks_single(plan.grams[0], slots, bm);
+        plan.grams[0].fused = plan.grams[0].nchunk == 1;
     }
     if (real) {
         const int maxlog = mode == M_F64 ? FFT_MAXLOG_F64 : FFT_MAXLOG_F32;
@@ -299,6 +303,8 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         off += g.plane_bytes * pl;
     }
     for (GramPlan &g : plan.grams) {
+        if (g.fused)
+            continue;
         g.part_off = off;
         off += align256((size_t)g.nslot * g.nupper * 2 * bm * bm * sizeof(double));
     }
@@ -323,7 +329,8 @@ void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd)
         d.nchunk = g.nchunk;
         d.chunk = g.chunk;
         d.nslot = g.nslot;
-        d.partial = (double *)(ws + g.part_off);
+        d.fused = g.fused ? 1 : 0;
+        d.partial = g.fused ? nullptr : (double *)(ws + g.part_off);
         d.plv = g.plv;
         d.iplv = g.iplv;
         d.ciplv = g.ciplv;
@@ -359,7 +366,7 @@ void build_tables(const Plan &plan, const std::vector<GramDesc> &gd, std::vector
         for (int c = 0; c < d.nchunk; ++c)
             for (int t = 0; t < d.nupper; ++t)
                 items.push_back(Item{(int32_t)q, t, c, 0});
-        if (!backward)
+        if (!backward && !d.fused)
             for (int t = 0; t < d.nupper; ++t)
                 tiles.push_back(TileRef{(int32_t)q, t});
     }

@@ -12,7 +12,7 @@
 namespace plv {
 
 constexpr int MAX_CHUNK = 16384;     // longest FP32 accumulation span of one work item (samples)
-constexpr int MIN_CHUNK = 1024;      // shortest K-chunk worth a work-group
+constexpr int MIN_CHUNK = 128;       // shortest K-chunk worth a work-group
 constexpr size_t PARTIAL_BUDGET = size_t(2) << 30;  // partial-slot bytes before T is split into passes
 
 struct GramPlan {
@@ -22,6 +22,7 @@ struct GramPlan {
     int t = 0, t0 = 0, tpad = 0;       // window length, window start, padded length
     int ntile = 0, nupper = 0;
     int nchunk = 0, chunk = 0, nslot = 0;
+    bool fused = false;                // one chunk: the Gram kernel stores the measures
     size_t u_off = 0, plane_bytes = 0; // phasor planes (backward: the H operand)
     size_t part_off = 0;               // FP64 partial sums
     // backward only: C = H (conj U^T)^H over the full tile grid
