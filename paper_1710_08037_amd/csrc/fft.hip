@@ -1,25 +1,36 @@
 // fft.hip -- analytic signal of real rows by FFT (Section II.A, Eq. 3), fused
 // with the window, the phasor normalisation (Eq. 4) and the store of the
-// Gram kernel's phasor planes.
+// Gram kernel's phasor planes; and its adjoint for the backward.
 //
 // For a row x of length t and each band b:
 //   X = DFT_t(x);  z_b = IDFT_t(h_b .* X);  u_b(s) = z_b(t0 + s) / |z_b(t0 + s)|
 // with h the one-sided weights of the discrete analytic signal (1 at DC, 2
 // below Nyquist, 1 at Nyquist for even t, 0 above) or a band mask (2 on the
 // positive-frequency bins [klo, khi], 0 elsewhere).  The transforms run at the
-// exact length t: radix-2 when t is a power of two, otherwise Bluestein's
-// chirp-z form, DFT_t(x)_k = conj(c_k) * (a (*) b)_k with c_m = exp(i pi m^2/t),
-// a = x .* conj(c) zero-padded to M >= 2t - 1 and b the circular chirp, the
-// circular convolution taken by length-M FFTs with FFT_M(b) precomputed once
-// per length.  The inverse uses IDFT(Y) = conj(DFT(conj(Y))) / t.
+// exact length t: an FFT of size M = t when t is a power of two, otherwise
+// Bluestein's chirp-z form, DFT_t(x)_k = conj(c_k) * (a (*) b)_k / M-scaled,
+// with c_m = exp(i pi m^2 / t), a = x .* conj(c) zero-padded to M >= 2t - 1
+// and b the circular chirp; the circular convolution is taken by length-M FFTs
+// with FFT_M(b) prepared once per length.  The inverse uses
+// IDFT(Y) = conj(DFT(conj(Y))) / t.
 //
-// One work-group per row at a time (grid-stride over the rows of one FFT
-// size): the row's spectrum X and a work buffer live in LDS with the twiddle
-// table.  Forward transforms are decimation-in-time from a bit-reversed load
-// (natural-order output); inverse transforms are decimation-in-frequency
-// (natural-order input, bit-reversed output), so no permutation passes are
-// needed between them.  Chirp angles are reduced exactly in integers
-// (m^2 mod 2t) and evaluated in FP64.
+// Transforms: Stockham autosort passes of radix 16 (one smaller radix pass
+// when log2 M is not a multiple of 4), in natural order throughout.  Each
+// active thread holds PER = 16 elements in registers -- element
+// tid + e * (M / PER) of the sequence -- and does whole radix-R butterflies on
+// them; between passes the sequence goes through LDS (one hole every 16
+// elements against bank conflicts).  Twiddles come from a quarter-wave table
+// exp(-2 pi i m / M), m < M/4, in LDS, rotated by powers of -i.
+//
+// Bands: X stays in registers (and in LDS) after the forward transform.  A
+// band whose bin count K is small relative to the FFT cost is synthesised
+// directly, z(n) = (2/t) sum_{k=klo..khi} X_k exp(2 pi i k n / t), as
+// exp(2 pi i klo n / t) times a Horner polynomial in exp(2 pi i n / t) read
+// from a per-length root table; other bands (and the plain analytic signal)
+// take the inverse transform.
+//
+// One work-group per row at a time, grid-stride over the rows of one FFT
+// size; one kernel instance per size, so LDS and the work-group shape fit M.
 #include "phasor.h"
 
 namespace plv {
@@ -55,360 +66,688 @@ __device__ inline cx<R> cscale(cx<R> a, R s)
     return cx<R>{a.x * s, a.y * s};
 }
 
-__device__ inline int brev(int n, int logm) { return (int)(__brev((unsigned)n) >> (32 - logm)); }
-
-constexpr int NT = 256;  // threads per work-group
-
-// In-place radix-2 DIT, forward (exp(-)), bit-reversed input -> natural output.
+// Global-memory access of complex elements as native 2-vectors (loads and
+// stores through global-address-space pointers).
 template <class R>
-__device__ void fft_dit(cx<R> *W, const cx<R> *TW, int logm)
+using v2_t = typename std::conditional<sizeof(R) == 8, vd2, vf2>::type;
+template <class R>
+__device__ inline cx<R> gld(const cx<R> *p, int64_t i)
 {
-    const int M = 1 << logm;
-    for (int s = 1; s <= logm; ++s) {
-        const int h = 1 << (s - 1), ts = M >> s;
-        for (int b = threadIdx.x; b < M / 2; b += NT) {
-            const int j = b & (h - 1);
-            const int i0 = ((b >> (s - 1)) << s) + j, i1 = i0 + h;
-            const cx<R> u = W[i0], v = cmul(W[i1], TW[j * ts]);
-            W[i0] = cadd(u, v);
-            W[i1] = csub(u, v);
+    const v2_t<R> a = gptr((const v2_t<R> *)p)[i];
+    return cx<R>{a.x, a.y};
+}
+template <class R>
+__device__ inline void gst(cx<R> *p, int64_t i, cx<R> a)
+{
+    gptr((v2_t<R> *)p)[i] = v2_t<R>{a.x, a.y};
+}
+
+// ------------------------------------------------------------ shapes --
+#ifndef PLV_FFT_LP
+#define PLV_FFT_LP 3
+#endif
+constexpr int LP = PLV_FFT_LP;  // log2 of the elements per thread (and of the main radix)
+__host__ __device__ constexpr int per_of(int logm) { return 1 << (logm < LP ? logm : LP); }
+__host__ __device__ constexpr int nta_of(int logm) { return (1 << logm) / per_of(logm); }  // active threads
+__host__ __device__ constexpr int nt_of(int logm) { return nta_of(logm) < 64 ? 64 : nta_of(logm); }
+__host__ __device__ constexpr int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int buf_elems(int logm) { return lpad((1 << logm) - 1) + 1; }
+__host__ __device__ constexpr int npass_of(int logm) { return logm <= LP ? 1 : logm / LP + (logm % LP ? 1 : 0); }
+// log2 of pass p's radix; the full-radix passes come first
+__host__ __device__ constexpr int lrad_of(int logm, int p) { return logm <= LP ? logm : (p < logm / LP ? LP : logm % LP); }
+
+// a * exp(-+2 pi i m / 16) (forward: minus), m a constant after unrolling.
+template <class R, bool INV>
+__device__ inline cx<R> rot16(cx<R> a, int m)
+{
+    m &= 15;
+    if (m == 0)
+        return a;
+    if (m == 8)
+        return cx<R>{-a.x, -a.y};
+    if (m == 4)  // forward: * (-i)
+        return INV ? cx<R>{-a.y, a.x} : cx<R>{a.y, -a.x};
+    if (m == 12)  // forward: * (+i)
+        return INV ? cx<R>{a.y, -a.x} : cx<R>{-a.y, a.x};
+    // cos and sin of 2 pi m / 16
+    constexpr R C1 = (R)0.92387953251128675613;  // cos(pi / 8)
+    constexpr R S1 = (R)0.38268343236508977173;  // sin(pi / 8)
+    constexpr R H = (R)0.70710678118654752440;   // sqrt(1/2)
+    R c, s;
+    switch (m) {
+    case 1: c = C1; s = S1; break;
+    case 2: c = H; s = H; break;
+    case 3: c = S1; s = C1; break;
+    case 5: c = -S1; s = C1; break;
+    case 6: c = -H; s = H; break;
+    case 7: c = -C1; s = S1; break;
+    case 9: c = -C1; s = -S1; break;
+    case 10: c = -H; s = -H; break;
+    case 11: c = -S1; s = -C1; break;
+    case 13: c = S1; s = -C1; break;
+    case 14: c = H; s = -H; break;
+    default: c = C1; s = -S1; break;  // 15
+    }
+    const R sg = INV ? s : -s;
+    return cx<R>{a.x * c - a.y * sg, a.x * sg + a.y * c};
+}
+
+// In-register DFT of N = 1, 2, 4, 8, 16 points, natural order in and out
+// (forward exp(-), inverse exp(+), unscaled).  N = 4 N2 splits as
+// n = N2 n1 + n2, k = k1 + 4 k2: length-4 DFTs over n1, twiddles
+// W_N^(n2 k1), length-N2 DFTs over n2.
+template <class R, bool INV, int N>
+__device__ inline void dft(cx<R> (&v)[N])
+{
+    if constexpr (N == 1) {
+        return;
+    } else if constexpr (N == 2) {
+        const cx<R> a = v[0];
+        v[0] = cadd(a, v[1]);
+        v[1] = csub(a, v[1]);
+    } else if constexpr (N == 4) {
+        const cx<R> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        const cx<R> a2 = cadd(v[1], v[3]), a3 = rot16<R, INV>(csub(v[1], v[3]), 4);
+        v[0] = cadd(a0, a2);
+        v[2] = csub(a0, a2);
+        v[1] = cadd(a1, a3);
+        v[3] = csub(a1, a3);
+    } else {
+        constexpr int N2 = N / 4;
+        cx<R> a[N2][4];
+#pragma unroll
+        for (int n2 = 0; n2 < N2; ++n2) {
+            cx<R> s[4] = {v[n2], v[N2 + n2], v[2 * N2 + n2], v[3 * N2 + n2]};
+            dft<R, INV, 4>(s);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1)
+                a[n2][k1] = rot16<R, INV>(s[k1], n2 * k1 * (16 / N));
         }
-        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cx<R> s[N2];
+#pragma unroll
+            for (int n2 = 0; n2 < N2; ++n2)
+                s[n2] = a[n2][k1];
+            dft<R, INV, N2>(s);
+#pragma unroll
+            for (int k2 = 0; k2 < N2; ++k2)
+                v[k1 + 4 * k2] = s[k2];
+        }
     }
 }
 
-// In-place radix-2 DIF, inverse (exp(+)), natural input -> bit-reversed
-// output, unscaled.
-template <class R>
-__device__ void ifft_dif(cx<R> *W, const cx<R> *TW, int logm)
+// exp(-+2 pi i idx / M) for 0 <= idx < M from the quarter-wave table.
+template <class R, bool INV, int LOGM>
+__device__ inline cx<R> twiddle(const cx<R> *twq, int idx)
 {
-    const int M = 1 << logm;
-    for (int s = logm; s >= 1; --s) {
-        const int h = 1 << (s - 1), ts = M >> s;
-        for (int b = threadIdx.x; b < M / 2; b += NT) {
-            const int j = b & (h - 1);
-            const int i0 = ((b >> (s - 1)) << s) + j, i1 = i0 + h;
-            const cx<R> u = W[i0], v = W[i1];
-            W[i0] = cadd(u, v);
-            W[i1] = cmul(csub(u, v), cconj(TW[j * ts]));
-        }
-        __syncthreads();
-    }
+    constexpr int Q = LOGM - 2;
+    const int q = idx >> Q;
+    const cx<R> w = twq[idx & ((1 << Q) - 1)];
+    cx<R> o = (q & 1) ? cx<R>{w.y, -w.x} : w;  // times -i
+    if (q & 2)
+        o = cx<R>{-o.x, -o.y};                  // times -1
+    if (INV)
+        o.y = -o.y;
+    return o;
 }
 
+// The twiddle table seen through an opaque zero offset, taken anew by each
+// transform: without it the compiler hoists every twiddle load of every
+// transform out of the row loop and keeps the values live across it, which
+// costs more registers than the reloads cost LDS bandwidth.
+template <class R>
+__device__ inline const cx<R> *opaque_table(const cx<R> *twq)
+{
+    int z;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
+    return twq + z;
+}
+
+// LDS index of element tid + e NTA (the natural register pattern); a base
+// plus constants when NTA is a multiple of 16.
+template <int LOGM>
+__device__ inline int pat_addr(int tid, int e)
+{
+    constexpr int NTA = nta_of(LOGM);
+    if constexpr (NTA % 16 == 0)
+        return lpad(tid) + e * (NTA + NTA / 16);
+    else
+        return lpad(tid + e * NTA);
+}
+
+// Stockham pass P: butterflies j = tid + q NTA (q < PER / RR) read elements
+// j + r M / RR -- registers e = q + r PER / RR of the natural pattern --, are
+// twiddled by W_(NS RR)^(r (j mod NS)) and transformed, and land at
+// (j - j mod NS) RR + j mod NS + r NS.
+template <class R, int LOGM, bool INV, int P>
+__device__ inline void fft_pass(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R> *twq, bool act)
+{
+    constexpr int PER = per_of(LOGM), NTA = nta_of(LOGM);
+    constexpr int LR = lrad_of(LOGM, P), RR = 1 << LR, NS = 1 << (LP * P), BPT = PER / RR;
+    const int tid = threadIdx.x;
+    if constexpr (P > 0) {
+        __syncthreads();  // the previous pass is in LDS
+        if (act) {
+#pragma unroll
+            for (int e = 0; e < PER; ++e)
+                v[e] = buf[pat_addr<LOGM>(tid, e)];
+        }
+    }
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            cx<R> b[RR];
+#pragma unroll
+            for (int r = 0; r < RR; ++r)
+                b[r] = v[q + r * BPT];
+            if constexpr (NS > 1) {
+                const int kk = (tid + q * NTA) & (NS - 1);
+#pragma unroll
+                for (int r = 1; r < RR; ++r)
+                    b[r] = cmul(b[r], twiddle<R, INV, LOGM>(twq, (r * kk) << (LOGM - LP * P - LR)));
+            }
+            dft<R, INV, RR>(b);
+#pragma unroll
+            for (int r = 0; r < RR; ++r)
+                v[q + r * BPT] = b[r];
+        }
+    }
+    __syncthreads();  // every thread has read this pass's input
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int j = tid + q * NTA, kk = j & (NS - 1);
+            const int d = ((j - kk) << LR) + kk;
+            // lpad(d + r NS) as a base plus constants where that is exact:
+            // NS >= 16 adds whole 16-groups; NS = 1 stays inside d's group
+            const int base = lpad(d);
+#pragma unroll
+            for (int r = 0; r < RR; ++r) {
+                const int adr = NS >= 16 ? base + r * (NS + NS / 16) : (NS == 1 ? base + r : lpad(d + r * NS));
+                buf[adr] = v[q + r * BPT];
+            }
+        }
+    }
+    if constexpr (P + 1 < npass_of(LOGM))
+        fft_pass<R, LOGM, INV, P + 1>(v, buf, twq, act);
+}
+
+// Transform of the sequence held in v (natural pattern); the result is left
+// in buf in natural order (index lpad(k)), visible to the whole work-group.
+// Every thread of the work-group must call it.
+template <class R, int LOGM, bool INV>
+__device__ inline void fft_lds(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R> *twq, bool act)
+{
+    fft_pass<R, LOGM, INV, 0>(v, buf, opaque_table(twq), act);
+    __syncthreads();
+}
+
+// ------------------------------------------------------- set-up kernels --
 // TW[k] = exp(-2 pi i k / M), k < M/2, evaluated in FP64.
 template <class R>
-__global__ __launch_bounds__(NT) void twiddle_kernel(cx<R> *tab, int logm)
+__global__ __launch_bounds__(256) void twiddle_kernel(cx<R> *tab, int logm)
 {
     const int M = 1 << logm;
-    for (int k = blockIdx.x * NT + threadIdx.x; k < M / 2; k += gridDim.x * NT) {
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < M / 2; k += gridDim.x * 256) {
         double sn, cs;
         sincospi(-2.0 * (double)k / (double)M, &sn, &cs);
         tab[k] = cx<R>{(R)cs, (R)sn};
     }
 }
 
-// Chirp c_m = exp(i pi m^2 / t) for m < t and the circular chirp b of length
-// M: b_m = c_m (m < t), b_{M-m} = c_m (0 < m < t), 0 elsewhere; then
-// FFT_M(b) in place.  One work-group per job.
-template <class R, int MAXLOG>
-__global__ __launch_bounds__(NT) void chirp_kernel(const ChirpJob *jobs)
+template <class R, int LOGM>
+__device__ inline void load_quarter(cx<R> *twq, const void *tw_tab)
 {
-    __shared__ cx<R> W[1 << MAXLOG];
-    __shared__ cx<R> TW[(1 << MAXLOG) / 2];
-    const ChirpJob jb = jobs[blockIdx.x];
-    const int t = jb.t, logm = jb.logm, M = 1 << logm;
-    cx<R> *chirp = (cx<R> *)jb.chirp, *bh = (cx<R> *)jb.bhat;
-    for (int k = threadIdx.x; k < M / 2; k += NT) {
-        double sn, cs;
-        sincospi(-2.0 * (double)k / (double)M, &sn, &cs);
-        TW[k] = cx<R>{(R)cs, (R)sn};
+    constexpr int M = 1 << LOGM;
+    if constexpr (LOGM >= 2) {
+        const cx<R> *tg = (const cx<R> *)tw_tab;
+        for (int k = threadIdx.x; k < M / 4; k += blockDim.x)
+            twq[k] = tg[k];
     }
-    for (int m = threadIdx.x; m < M; m += NT) {
-        const int src = m < t ? m : (M - m < t ? M - m : -1);
-        cx<R> v{0, 0};
-        if (src >= 0) {
-            const int64_t r = ((int64_t)src * src) % (2 * (int64_t)t);  // m^2 mod 2t, exact
-            double sn, cs;
-            sincospi((double)r / (double)t, &sn, &cs);
-            v = cx<R>{(R)cs, (R)sn};
-            if (m < t)
-                chirp[m] = v;
-        }
-        W[brev(m, logm)] = v;
-    }
-    __syncthreads();
-    fft_dit(W, TW, logm);
-    for (int k = threadIdx.x; k < M; k += NT)
-        bh[k] = W[k];
 }
 
-template <int MODE>
-__global__ __launch_bounds__(NT) void hilbert_kernel(HilbertArgs a)
+// Per distinct row length t (one work-group per job): the root table
+// exp(2 pi i m / t), m < t; for Bluestein lengths also the chirp
+// c_m = exp(i pi m^2 / t), m < t, and FFT_M of the circular chirp
+// b_m = c_m (m < t), b_{M-m} = c_m (0 < m < t), 0 elsewhere.  Angles are
+// reduced exactly in integers (m^2 mod 2t) and evaluated in FP64.
+template <class R, int LOGM>
+__global__ __launch_bounds__(nt_of(LOGM)) void chirp_kernel(const ChirpJob *jobs)
 {
-    typedef typename std::conditional<MODE == M_F64, double, float>::type R;
-    constexpr int MAXLOG = MODE == M_F64 ? FFT_MAXLOG_F64 : FFT_MAXLOG_F32;
-    __shared__ cx<R> X[1 << MAXLOG];   // spectrum of the current row
-    __shared__ cx<R> W[1 << MAXLOG];   // work buffer
-    __shared__ cx<R> TW[(1 << MAXLOG) / 2];
+    constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
+    __shared__ cx<R> buf[buf_elems(LOGM)];
+    __shared__ cx<R> twq[M / 4 > 0 ? M / 4 : 1];
+    const ChirpJob jb = jobs[blockIdx.x];
+    const int t = jb.t, tid = threadIdx.x;
+    cx<R> *roots = (cx<R> *)jb.roots;
+    for (int m = tid; m < t; m += blockDim.x) {
+        double sn, cs;
+        sincospi(2.0 * (double)m / (double)t, &sn, &cs);
+        gst(roots, m, cx<R>{(R)cs, (R)sn});
+    }
+    if (!jb.blue)
+        return;
+    load_quarter<R, LOGM>(twq, jb.tw_tab);
+    cx<R> *chirp = (cx<R> *)jb.chirp, *bh = (cx<R> *)jb.bhat;
+    const bool act = tid < NTA;
+    cx<R> v[PER];
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+        const int m = tid + e * NTA;
+        const int src = m < t ? m : (M - m < t ? M - m : -1);
+        cx<R> c{0, 0};
+        if (act && src >= 0) {
+            const int64_t r2 = ((int64_t)src * src) % (2 * (int64_t)t);  // m^2 mod 2t, exact
+            double sn, cs;
+            sincospi((double)r2 / (double)t, &sn, &cs);
+            c = cx<R>{(R)cs, (R)sn};
+            if (m < t)
+                gst(chirp, m, c);
+        }
+        v[e] = c;
+    }
+    __syncthreads();  // twq
+    fft_lds<R, LOGM, false>(v, buf, twq, act);
+    for (int k = tid; k < M; k += blockDim.x)
+        gst(bh, k, buf[lpad(k)]);
+}
 
-    const int logm = a.logm, M = 1 << logm;
-    bool tw_loaded = false;
+// ------------------------------------------------------------- forward --
+template <class R>
+__device__ inline R band_weight(BandBins bb, int k, int t)
+{
+    if (bb.klo < 0)
+        return k == 0 ? (R)1 : (2 * k < t ? (R)2 : (2 * k == t ? (R)1 : (R)0));
+    return (k >= bb.klo && k <= bb.khi) ? (R)2 : (R)0;
+}
+
+template <class R>
+__device__ inline void store4_mode(int mode, uint8_t *dst, int64_t plane_bytes, const R (&ur)[4], const R (&ui)[4])
+{
+    if constexpr (sizeof(R) == 8) {
+        store4<M_F64>(dst, plane_bytes, ur, ui);
+    } else {
+        switch (mode) {
+        case M_F32: store4<M_F32>(dst, plane_bytes, ur, ui); break;
+        case M_SPLIT: store4<M_SPLIT>(dst, plane_bytes, ur, ui); break;
+        case M_BF16: store4<M_BF16>(dst, plane_bytes, ur, ui); break;
+        default: store4<M_F16>(dst, plane_bytes, ur, ui); break;
+        }
+    }
+}
+
+// Window samples of one band from z_n = zf(n) (a functor on the full-row
+// index n = t0 + s): phasor planes, or z itself for the backward.
+template <class R, class ZF>
+__device__ inline void store_band(int mode, const GramDesc &g, const HilbertProb &hp, int row, ZF zf)
+{
+    const int nt = blockDim.x;
+    if (g.zbuf) {
+        cx<R> *zr = (cx<R> *)g.zbuf + (int64_t)row * g.ldz;
+        for (int s = threadIdx.x; s < hp.tw; s += nt)
+            gst(zr, s, zf(hp.t0 + s));
+        return;
+    }
+    uint8_t *urow = (uint8_t *)g.u + (int64_t)row * g.ldu * cbytes_of(mode);
+    for (int s0 = threadIdx.x * 4; s0 < g.tpad; s0 += nt * 4) {
+        R ur[4], ui[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int s = s0 + v;
+            ur[v] = 0;
+            ui[v] = 0;
+            if (s < hp.tw) {
+                const cx<R> z = zf(hp.t0 + s);
+                unit_phasor(z.x, z.y, ur[v], ui[v]);
+            }
+        }
+        store4_mode<R>(mode, urow + (int64_t)s0 * cbytes_of(mode), g.plane_bytes, ur, ui);
+    }
+}
+
+// Direct synthesis of a narrow band from the spectrum in LDS:
+// z(n) = (2/t) exp(2 pi i klo n / t) sum_{m < K} X_{klo+m} w^m, w = exp(2 pi i n / t),
+// four consecutive window samples per thread step so that each X_k read
+// serves four.  The root index klo n mod t is carried from step to step.
+template <class R>
+__device__ inline void direct_band(int mode, const GramDesc &g, const HilbertProb &hp, int row, BandBins bb,
+                                   const cx<R> *buf)
+{
+    const int nt = blockDim.x, t = hp.t;
+    const cx<R> *roots = (const cx<R> *)hp.roots;
+    const R scale = (R)2 / (R)t;
+    const int klo = bb.klo, khi = bb.khi;
+    const bool empty = klo > khi;
+    const int kl = empty ? 0 : klo;  // keeps the root index in range for an empty band
+    // root index of the thread's first sample and its advance per step
+    const int s_first = threadIdx.x * 4;
+    int idx = (int)(((int64_t)kl * (hp.t0 + s_first)) % t);
+    const int step = (int)(((int64_t)kl * 4 * nt) % t);
+    const int limit = g.zbuf ? hp.tw : g.tpad;
+    cx<R> *zrow = (cx<R> *)g.zbuf + (int64_t)row * g.ldz;
+    uint8_t *urow = (uint8_t *)g.u + (int64_t)row * g.ldu * cbytes_of(mode);
+    for (int s0 = s_first; s0 < limit; s0 += nt * 4) {
+        cx<R> w[4], acc[4], base[4];
+        int ix = idx;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int n = min(hp.t0 + s0 + v, t - 1);  // clamped: samples past the window are discarded
+            w[v] = gld(roots, n);
+            base[v] = gld(roots, ix);
+            acc[v] = cx<R>{0, 0};
+            ix += kl;
+            ix = ix >= t ? ix - t : ix;
+        }
+        idx += step;
+        idx = idx >= t ? idx - t : idx;
+        for (int k = khi; k >= klo; --k) {
+            const cx<R> xk = buf[lpad(k)];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[v] = cadd(cmul(acc[v], w[v]), xk);
+        }
+        cx<R> z[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            z[v] = cscale(cmul(base[v], acc[v]), scale);  // 0 for an empty band
+        if (g.zbuf) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (s0 + v < hp.tw)
+                    gst(zrow, s0 + v, z[v]);
+        } else {
+            R ur[4], ui[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                ur[v] = 0;
+                ui[v] = 0;
+                if (s0 + v < hp.tw)
+                    unit_phasor(z[v].x, z[v].y, ur[v], ui[v]);
+            }
+            store4_mode<R>(mode, urow + (int64_t)s0 * cbytes_of(mode), g.plane_bytes, ur, ui);
+        }
+    }
+}
+
+template <class R, int LOGM>
+__global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int mode)
+{
+    constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
+    __shared__ cx<R> buf[buf_elems(LOGM)];
+    __shared__ cx<R> twq[M / 4 > 0 ? M / 4 : 1];
+    const int tid = threadIdx.x;
+    const bool act = tid < NTA;
+    load_quarter<R, LOGM>(twq, a.hp[a.rows[0].prob].tw_tab);  // one table per launch (one M)
+    __syncthreads();
+
     for (int ri = blockIdx.x; ri < a.nrows; ri += gridDim.x) {
         const RowRef rr = a.rows[ri];
         const HilbertProb hp = a.hp[rr.prob];
-        if (!tw_loaded) {
-            const cx<R> *tg = (const cx<R> *)hp.tw_tab;
-            for (int k = threadIdx.x; k < M / 2; k += NT)
-                TW[k] = tg[k];
-            tw_loaded = true;
-        }
         const int t = hp.t;
-        const R *x = (const R *)hp.x + (int64_t)rr.row * hp.ld;
+        auto x = gptr((const R *)hp.x + (int64_t)rr.row * hp.ld);
         const cx<R> *ch = (const cx<R> *)hp.chirp;
         const cx<R> *bh = (const cx<R> *)hp.bhat;
-        __syncthreads();  // TW visible; previous row done with X and W
+        cx<R> v[PER], X[PER];
+        // loads are unconditional at clamped indices, then selected
+        const int tid0 = act ? tid : 0;
 
-        // ---- X = DFT_t(x), natural order, k < t
+        // ---- X = DFT_t(x): natural order in buf (k < t) and in X (pattern)
         if (!hp.blue) {
-            for (int n = threadIdx.x; n < M; n += NT)
-                W[brev(n, logm)] = cx<R>{x[n], (R)0};
-            __syncthreads();
-            fft_dit(W, TW, logm);
-            for (int k = threadIdx.x; k < M; k += NT)
-                X[k] = W[k];
+#pragma unroll
+            for (int e = 0; e < PER; ++e)
+                v[e] = cx<R>{x[tid0 + e * NTA], (R)0};
+            fft_lds<R, LOGM, false>(v, buf, twq, act);
+#pragma unroll
+            for (int e = 0; e < PER; ++e)
+                X[e] = buf[pat_addr<LOGM>(tid0, e)];
         } else {
-            for (int n = threadIdx.x; n < M; n += NT) {
-                cx<R> v{0, 0};
-                if (n < t)
-                    v = cscale(cconj(ch[n]), x[n]);
-                W[brev(n, logm)] = v;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const int n = tid0 + e * NTA, nc = min(n, t - 1);
+                const cx<R> a = cscale(cconj(gld(ch, nc)), x[nc]);
+                v[e] = n < t ? a : cx<R>{0, 0};
+            }
+            fft_lds<R, LOGM, false>(v, buf, twq, act);
+#pragma unroll
+            for (int e = 0; e < PER; ++e)
+                v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
+            fft_lds<R, LOGM, true>(v, buf, twq, act);
+            const R invm = (R)1 / (R)M;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const int k = tid0 + e * NTA;
+                const cx<R> a = cscale(cmul(cconj(gld(ch, min(k, t - 1))), buf[pat_addr<LOGM>(tid0, e)]), invm);
+                X[e] = k < t ? a : cx<R>{0, 0};
+            }
+            __syncthreads();  // buf fully read
+            if (act) {
+#pragma unroll
+                for (int e = 0; e < PER; ++e)
+                    buf[pat_addr<LOGM>(tid, e)] = X[e];
             }
             __syncthreads();
-            fft_dit(W, TW, logm);
-            for (int k = threadIdx.x; k < M; k += NT)
-                W[k] = cmul(W[k], bh[k]);
-            __syncthreads();
-            ifft_dif(W, TW, logm);
-            const R invm = (R)1 / (R)M;
-            for (int k = threadIdx.x; k < t; k += NT)
-                X[k] = cscale(cmul(cconj(ch[k]), W[brev(k, logm)]), invm);
         }
-        __syncthreads();
 
-        // ---- each band: z = IDFT_t(h .* X), window, normalise, store planes
+        // ---- narrow bands straight from the bins in buf
         for (int b = 0; b < hp.nbands; ++b) {
             const BandBins bb = a.bins[hp.bin0 + b];
-            auto weight = [&](int k) -> R {
-                if (bb.klo < 0)
-                    return k == 0 ? (R)1 : (2 * k < t ? (R)2 : (2 * k == t ? (R)1 : (R)0));
-                return (k >= bb.klo && k <= bb.khi) ? (R)2 : (R)0;
-            };
-            R zscale;
-            if (!hp.blue) {
-                for (int k = threadIdx.x; k < M; k += NT)
-                    W[k] = cscale(X[k], weight(k));
-                __syncthreads();
-                ifft_dif(W, TW, logm);  // z_n = W[brev(n)] / t
-                zscale = (R)1 / (R)t;
-            } else {
-                // v = conj(Y) with Y = h .* X; Bluestein DFT of v; z = conj(DFT(v)) / t
-                for (int n = threadIdx.x; n < M; n += NT) {
-                    cx<R> v{0, 0};
-                    if (n < t)
-                        v = cconj(cmul(cscale(X[n], weight(n)), ch[n]));
-                    W[brev(n, logm)] = v;
-                }
-                __syncthreads();
-                fft_dit(W, TW, logm);
-                for (int k = threadIdx.x; k < M; k += NT)
-                    W[k] = cmul(W[k], bh[k]);
-                __syncthreads();
-                ifft_dif(W, TW, logm);  // z_n = c_n conj(W[brev(n)]) / (M t)
-                zscale = (R)1 / ((R)M * (R)t);
-            }
-            const GramDesc g = a.gd[hp.gram0 + b];
-            if (g.zbuf) {
-                // backward: keep the analytic signal itself on the window
-                cx<R> *zr = (cx<R> *)g.zbuf + (int64_t)rr.row * g.ldz;
-                for (int s = threadIdx.x; s < hp.tw; s += NT) {
-                    const int n = hp.t0 + s;
-                    cx<R> z = W[brev(n, logm)];
-                    if (hp.blue)
-                        z = cmul(ch[n], cconj(z));
-                    zr[s] = cscale(z, zscale);
-                }
-                __syncthreads();
+            if (bb.direct)
+                direct_band<R>(mode, a.gd[hp.gram0 + b], hp, rr.row, bb, buf);
+        }
+        // ---- the other bands by inverse transform (each overwrites buf)
+        for (int b = 0; b < hp.nbands; ++b) {
+            const BandBins bb = a.bins[hp.bin0 + b];
+            if (bb.direct)
                 continue;
-            }
-            uint8_t *urow = (uint8_t *)g.u + (int64_t)rr.row * g.ldu * cbytes_of(MODE);
-            for (int s0 = threadIdx.x * 4; s0 < g.tpad; s0 += NT * 4) {
-                R ur[4], ui[4];
+            const GramDesc g = a.gd[hp.gram0 + b];
+            if (!hp.blue) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int s = s0 + v;
-                    ur[v] = 0;
-                    ui[v] = 0;
-                    if (s < hp.tw) {
-                        const int n = hp.t0 + s;
-                        cx<R> z = W[brev(n, logm)];
-                        if (hp.blue)
-                            z = cmul(ch[n], cconj(z));
-                        unit_phasor(z.x * zscale, z.y * zscale, ur[v], ui[v]);
-                    }
+                for (int e = 0; e < PER; ++e)
+                    v[e] = cscale(X[e], band_weight<R>(bb, tid0 + e * NTA, t));
+                fft_lds<R, LOGM, true>(v, buf, twq, act);
+                const R inv_t = (R)1 / (R)t;
+                store_band<R>(mode, g, hp, rr.row, [&](int n) { return cscale(buf[lpad(n)], inv_t); });
+            } else {
+                // v = conj(Y), Y = h .* X; z = conj(DFT_t(v)) / t by Bluestein
+#pragma unroll
+                for (int e = 0; e < PER; ++e) {
+                    const int n = tid0 + e * NTA;
+                    // X is 0 at n >= t, so the clamped chirp index changes nothing
+                    v[e] = cconj(cmul(cscale(X[e], band_weight<R>(bb, n, t)), gld(ch, min(n, t - 1))));
                 }
-                store4<MODE>(urow + (int64_t)s0 * cbytes_of(MODE), g.plane_bytes, ur, ui);
+                fft_lds<R, LOGM, false>(v, buf, twq, act);
+#pragma unroll
+                for (int e = 0; e < PER; ++e)
+                    v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
+                fft_lds<R, LOGM, true>(v, buf, twq, act);
+                const R zs = (R)1 / ((R)M * (R)t);
+                store_band<R>(mode, g, hp, rr.row,
+                              [&](int n) { return cscale(cmul(gld(ch, n), cconj(buf[lpad(n)])), zs); });
             }
-            __syncthreads();  // W is rewritten by the next band
         }
     }
 }
 
+// -------------------------------------------------------------- adjoint --
 // dL/dx of one row: z_b = M_b x with M_b = IDFT diag(h_b) DFT Hermitian
 // (h_b real), so dL/dx = Re(sum_b M_b zbar_b) = Re(IDFT(sum_b h_b .*
-// DFT(zbar_b))), zbar_b being 0 outside the window.
-template <class R, int MAXLOG>
-__global__ __launch_bounds__(NT) void hilbert_adjoint_kernel(HilbertArgs a)
+// DFT(zbar_b))), zbar_b being 0 outside the window.  The spectrum sum S stays
+// in registers (natural pattern).
+template <class R, int LOGM>
+__global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArgs a)
 {
-    __shared__ cx<R> X[1 << MAXLOG];   // sum over bands of h_b .* DFT(zbar_b)
-    __shared__ cx<R> W[1 << MAXLOG];
-    __shared__ cx<R> TW[(1 << MAXLOG) / 2];
-    const int logm = a.logm, M = 1 << logm;
-    bool tw_loaded = false;
+    constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
+    __shared__ cx<R> buf[buf_elems(LOGM)];
+    __shared__ cx<R> twq[M / 4 > 0 ? M / 4 : 1];
+    const int tid = threadIdx.x;
+    const bool act = tid < NTA;
+    load_quarter<R, LOGM>(twq, a.hp[a.rows[0].prob].tw_tab);
+    __syncthreads();
+
     for (int ri = blockIdx.x; ri < a.nrows; ri += gridDim.x) {
         const RowRef rr = a.rows[ri];
         const HilbertProb hp = a.hp[rr.prob];
-        if (!tw_loaded) {
-            const cx<R> *tg = (const cx<R> *)hp.tw_tab;
-            for (int k = threadIdx.x; k < M / 2; k += NT)
-                TW[k] = tg[k];
-            tw_loaded = true;
-        }
         const int t = hp.t;
         const cx<R> *ch = (const cx<R> *)hp.chirp;
         const cx<R> *bh = (const cx<R> *)hp.bhat;
-        for (int k = threadIdx.x; k < M; k += NT)
-            X[k] = cx<R>{0, 0};
-        __syncthreads();
+        const int tid0 = act ? tid : 0;
+        cx<R> v[PER], S[PER];
+#pragma unroll
+        for (int e = 0; e < PER; ++e)
+            S[e] = cx<R>{0, 0};
         for (int b = 0; b < hp.nbands; ++b) {
             const BandBins bb = a.bins[hp.bin0 + b];
-            auto weight = [&](int k) -> R {
-                if (bb.klo < 0)
-                    return k == 0 ? (R)1 : (2 * k < t ? (R)2 : (2 * k == t ? (R)1 : (R)0));
-                return (k >= bb.klo && k <= bb.khi) ? (R)2 : (R)0;
-            };
             const GramDesc g = a.gd[hp.gram0 + b];
             const cx<R> *zb = (const cx<R> *)g.zbuf + (int64_t)rr.row * g.ldz;
             auto v_at = [&](int n) -> cx<R> {  // zbar on the full row, 0 off the window
                 const int s = n - hp.t0;
-                return (s >= 0 && s < hp.tw) ? zb[s] : cx<R>{0, 0};
+                const cx<R> z = gld(zb, min(max(s, 0), hp.tw - 1));
+                return (s >= 0 && s < hp.tw) ? z : cx<R>{0, 0};
             };
             if (!hp.blue) {
-                for (int n = threadIdx.x; n < M; n += NT)
-                    W[brev(n, logm)] = v_at(n);
-                __syncthreads();
-                fft_dit(W, TW, logm);
-                for (int k = threadIdx.x; k < M; k += NT)
-                    X[k] = cadd(X[k], cscale(W[k], weight(k)));
+#pragma unroll
+                for (int e = 0; e < PER; ++e)
+                    v[e] = v_at(tid0 + e * NTA);
+                fft_lds<R, LOGM, false>(v, buf, twq, act);
+#pragma unroll
+                for (int e = 0; e < PER; ++e)
+                    S[e] = cadd(S[e], cscale(buf[pat_addr<LOGM>(tid0, e)], band_weight<R>(bb, tid0 + e * NTA, t)));
             } else {
-                for (int n = threadIdx.x; n < M; n += NT) {
-                    cx<R> v{0, 0};
-                    if (n < t)
-                        v = cmul(v_at(n), cconj(ch[n]));
-                    W[brev(n, logm)] = v;
+#pragma unroll
+                for (int e = 0; e < PER; ++e) {
+                    const int n = tid0 + e * NTA;
+                    const cx<R> a = cmul(v_at(n), cconj(gld(ch, min(n, t - 1))));  // v_at is 0 at n >= t
+                    v[e] = a;
                 }
-                __syncthreads();
-                fft_dit(W, TW, logm);
-                for (int k = threadIdx.x; k < M; k += NT)
-                    W[k] = cmul(W[k], bh[k]);
-                __syncthreads();
-                ifft_dif(W, TW, logm);
+                fft_lds<R, LOGM, false>(v, buf, twq, act);
+#pragma unroll
+                for (int e = 0; e < PER; ++e)
+                    v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
+                fft_lds<R, LOGM, true>(v, buf, twq, act);
                 const R invm = (R)1 / (R)M;
-                for (int k = threadIdx.x; k < t; k += NT)
-                    X[k] = cadd(X[k], cscale(cmul(cconj(ch[k]), W[brev(k, logm)]), weight(k) * invm));
+#pragma unroll
+                for (int e = 0; e < PER; ++e) {
+                    const int k = tid0 + e * NTA;
+                    const cx<R> d = cmul(cconj(gld(ch, min(k, t - 1))), buf[pat_addr<LOGM>(tid0, e)]);
+                    S[e] = cadd(S[e], cscale(d, k < t ? band_weight<R>(bb, k, t) * invm : (R)0));
+                }
             }
-            __syncthreads();
         }
-        // x_bar = Re(IDFT_t(X))
-        R *xb = (R *)hp.xbar + (int64_t)rr.row * hp.ld;
+        // x_bar = Re(IDFT_t(S))
+        auto xb = gptr((R *)hp.xbar + (int64_t)rr.row * hp.ld);
         if (!hp.blue) {
-            for (int k = threadIdx.x; k < M; k += NT)
-                W[k] = X[k];
-            __syncthreads();
-            ifft_dif(W, TW, logm);
+#pragma unroll
+            for (int e = 0; e < PER; ++e)
+                v[e] = S[e];
+            fft_lds<R, LOGM, true>(v, buf, twq, act);
             const R inv_t = (R)1 / (R)t;
-            for (int n = threadIdx.x; n < t; n += NT)
-                xb[n] = W[brev(n, logm)].x * inv_t;
+            for (int n = tid; n < t; n += blockDim.x)
+                xb[n] = buf[lpad(n)].x * inv_t;
         } else {
-            // IDFT(X) = conj(DFT(conj X)) / t; only its real part is needed
-            for (int n = threadIdx.x; n < M; n += NT) {
-                cx<R> v{0, 0};
-                if (n < t)
-                    v = cconj(cmul(X[n], ch[n]));
-                W[brev(n, logm)] = v;
+            // IDFT(S) = conj(DFT(conj S)) / t; only its real part is needed
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+                const int n = tid0 + e * NTA;
+                v[e] = cconj(cmul(S[e], gld(ch, min(n, t - 1))));  // S is 0 at n >= t
             }
-            __syncthreads();
-            fft_dit(W, TW, logm);
-            for (int k = threadIdx.x; k < M; k += NT)
-                W[k] = cmul(W[k], bh[k]);
-            __syncthreads();
-            ifft_dif(W, TW, logm);
+            fft_lds<R, LOGM, false>(v, buf, twq, act);
+#pragma unroll
+            for (int e = 0; e < PER; ++e)
+                v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
+            fft_lds<R, LOGM, true>(v, buf, twq, act);
             const R scale = (R)1 / ((R)M * (R)t);
-            for (int n = threadIdx.x; n < t; n += NT)
-                xb[n] = cmul(cconj(ch[n]), W[brev(n, logm)]).x * scale;
+            for (int n = tid; n < t; n += blockDim.x)
+                xb[n] = cmul(cconj(gld(ch, n)), buf[lpad(n)]).x * scale;
         }
-        __syncthreads();
     }
+}
+
+// ------------------------------------------------------------ dispatch --
+template <class K>
+int grid_for(K kernel, int nt, int rows, int cus)
+{
+    int occ = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, nt, 0) != hipSuccess || occ < 1)
+        occ = 1;
+    return std::max(1, std::min(rows, cus * occ));
+}
+
+template <class R, int LOGM>
+hipError_t launch_sized(int kind, int mode, const HilbertArgs *ha, const ChirpJob *jobs, int n, int cus,
+                        hipStream_t s)
+{
+    constexpr int NT = nt_of(LOGM);
+    if (kind == 0) {
+        chirp_kernel<R, LOGM><<<n, NT, 0, s>>>(jobs);
+    } else if (kind == 1) {
+        const int nwg = grid_for(hilbert_kernel<R, LOGM>, NT, ha->nrows, cus);
+        hilbert_kernel<R, LOGM><<<nwg, NT, 0, s>>>(*ha, mode);
+    } else {
+        const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM>, NT, ha->nrows, cus);
+        hilbert_adjoint_kernel<R, LOGM><<<nwg, NT, 0, s>>>(*ha);
+    }
+    return hipGetLastError();
+}
+
+template <class R, int LOGM, int MAXLOG>
+hipError_t dispatch(int logm, int kind, int mode, const HilbertArgs *ha, const ChirpJob *jobs, int n, int cus,
+                    hipStream_t s)
+{
+    if (logm == LOGM)
+        return launch_sized<R, LOGM>(kind, mode, ha, jobs, n, cus, s);
+    if constexpr (LOGM < MAXLOG)
+        return dispatch<R, LOGM + 1, MAXLOG>(logm, kind, mode, ha, jobs, n, cus, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t dispatch_any(bool f64, int logm, int kind, int mode, const HilbertArgs *ha, const ChirpJob *jobs, int n,
+                        int cus, hipStream_t s)
+{
+    if (f64) {
+        if (logm < 1 || logm > FFT_MAXLOG_F64)
+            return hipErrorInvalidValue;
+        return dispatch<double, 1, FFT_MAXLOG_F64>(logm, kind, mode, ha, jobs, n, cus, s);
+    }
+    if (logm < 1 || logm > FFT_MAXLOG_F32)
+        return hipErrorInvalidValue;
+    return dispatch<float, 1, FFT_MAXLOG_F32>(logm, kind, mode, ha, jobs, n, cus, s);
 }
 
 }  // namespace
 
-hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int nwg, hipStream_t s)
-{
-    if (nwg <= 0 || a.nrows <= 0)
-        return hipSuccess;
-    if (f64)
-        hilbert_adjoint_kernel<double, FFT_MAXLOG_F64><<<nwg, NT, 0, s>>>(a);
-    else
-        hilbert_adjoint_kernel<float, FFT_MAXLOG_F32><<<nwg, NT, 0, s>>>(a);
-    return hipGetLastError();
-}
-
 hipError_t launch_twiddles(bool f64, void *tab, int logm, hipStream_t s)
 {
     const int half = (1 << logm) / 2;
-    const int grid = std::max(1, std::min(64, (half + NT - 1) / NT));
+    const int grid = std::max(1, std::min(64, (half + 255) / 256));
     if (f64)
-        twiddle_kernel<double><<<grid, NT, 0, s>>>((cx<double> *)tab, logm);
+        twiddle_kernel<double><<<grid, 256, 0, s>>>((cx<double> *)tab, logm);
     else
-        twiddle_kernel<float><<<grid, NT, 0, s>>>((cx<float> *)tab, logm);
+        twiddle_kernel<float><<<grid, 256, 0, s>>>((cx<float> *)tab, logm);
     return hipGetLastError();
 }
 
-hipError_t launch_chirps(bool f64, const ChirpJob *jobs, int njobs, hipStream_t s)
+hipError_t launch_chirps(bool f64, int logm, const ChirpJob *jobs, int njobs, hipStream_t s)
 {
     if (njobs <= 0)
         return hipSuccess;
-    if (f64)
-        chirp_kernel<double, FFT_MAXLOG_F64><<<njobs, NT, 0, s>>>(jobs);
-    else
-        chirp_kernel<float, FFT_MAXLOG_F32><<<njobs, NT, 0, s>>>(jobs);
-    return hipGetLastError();
+    return dispatch_any(f64, logm, 0, 0, nullptr, jobs, njobs, 0, s);
 }
 
-hipError_t launch_hilbert(int mode, const HilbertArgs &a, int nwg, hipStream_t s)
+hipError_t launch_hilbert(int mode, const HilbertArgs &a, int cus, hipStream_t s)
 {
-    if (nwg <= 0 || a.nrows <= 0)
+    if (a.nrows <= 0)
         return hipSuccess;
-    switch (mode) {
-    case M_F64: hilbert_kernel<M_F64><<<nwg, NT, 0, s>>>(a); break;
-    case M_F32: hilbert_kernel<M_F32><<<nwg, NT, 0, s>>>(a); break;
-    case M_SPLIT: hilbert_kernel<M_SPLIT><<<nwg, NT, 0, s>>>(a); break;
-    case M_BF16: hilbert_kernel<M_BF16><<<nwg, NT, 0, s>>>(a); break;
-    case M_F16: hilbert_kernel<M_F16><<<nwg, NT, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    if (mode < M_F64 || mode > M_F16)
+        return hipErrorInvalidValue;
+    return dispatch_any(mode == M_F64, a.logm, 1, mode, &a, nullptr, 0, cus, s);
+}
+
+hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int cus, hipStream_t s)
+{
+    if (a.nrows <= 0)
+        return hipSuccess;
+    return dispatch_any(f64, a.logm, 2, f64 ? M_F64 : M_F32, &a, nullptr, 0, cus, s);
 }
 
 }  // namespace plv

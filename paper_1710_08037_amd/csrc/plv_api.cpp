@@ -307,6 +307,107 @@ static BandBins band_bins(int t, double fs, const plv_band *band)
     return BandBins{klo, khi};
 }
 
+// Direct synthesis of a band costs about 4 K + 12 operations per output
+// sample (K bins); the inverse transform about (2.5 log2 M + 6) M / t per
+// sample, twice for a Bluestein length.  The cheaper one is taken.
+static bool direct_band(const FftPlan &f, BandBins bb)
+{
+    if (bb.klo < 0)
+        return false;  // plain analytic signal: every positive bin
+    const int k = bb.khi >= bb.klo ? bb.khi - bb.klo + 1 : 0;
+    const double direct = 4.0 * k + 12.0;
+    const double fft = (f.blue ? 2.0 : 1.0) * (double)(1 << f.logm) / (double)f.t * (2.5 * f.logm + 6.0);
+    return direct < fft;
+}
+
+// Host tables of the FFT stage in the upload blob: problems, band bins, rows
+// grouped by FFT size (class_start / class_count per size), per-length jobs.
+static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const plv_grad *grads,
+                            const plv_band *bands, int nbands, double fs, uint8_t *ws, std::vector<uint8_t> &blob,
+                            std::vector<int> &class_start, std::vector<int> &class_count)
+{
+    const size_t nprob = plan.fft.size();
+    HilbertProb *hp = (HilbertProb *)(blob.data() + plan.hp_off);
+    BandBins *bins = (BandBins *)(blob.data() + plan.bin_off);
+    RowRef *rows = (RowRef *)(blob.data() + plan.row_off);
+    ChirpJob *jobs = (ChirpJob *)(blob.data() + plan.job_off);
+    for (size_t q = 0; q < nprob; ++q) {
+        const FftPlan &f = plan.fft[q];
+        const LenPlan &l = plan.lens[f.len_index];
+        const plv_problem &p = probs[q];
+        HilbertProb h{};
+        h.x = p.in;
+        h.ld = p.ld;
+        h.n = (int32_t)p.n;
+        h.t = f.t;
+        h.t0 = (int32_t)p.t0;
+        h.tw = plan.grams[q * nbands].t;
+        h.logm = f.logm;
+        h.blue = f.blue ? 1 : 0;
+        h.chirp = f.blue ? ws + l.chirp_off : nullptr;
+        h.bhat = f.blue ? ws + l.bhat_off : nullptr;
+        h.tw_tab = ws + plan.tw_off[f.tw_index];
+        h.roots = ws + l.roots_off;
+        h.gram0 = (int32_t)(q * nbands);
+        h.nbands = nbands;
+        h.bin0 = (int32_t)(q * nbands);
+        h.xbar = grads ? grads[q].din : nullptr;
+        hp[q] = h;
+        for (int b = 0; b < nbands; ++b) {
+            BandBins bb = band_bins(f.t, fs, bands ? &bands[b] : nullptr);
+            // (the adjoint kernel takes every band through the transform)
+            bb.direct = direct_band(f, bb) ? 1 : 0;
+            bins[q * nbands + b] = bb;
+        }
+    }
+    size_t r = 0;
+    for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+        class_start.push_back((int)r);
+        for (size_t q = 0; q < nprob; ++q)
+            if (plan.fft[q].logm == plan.tw_logm[c])
+                for (int64_t i = 0; i < probs[q].n; ++i)
+                    rows[r++] = RowRef{(int32_t)q, (int32_t)i};
+        class_count.push_back((int)r - class_start.back());
+    }
+    for (size_t c = 0; c < plan.lens.size(); ++c) {
+        const LenPlan &l = plan.lens[c];
+        const size_t ti = std::find(plan.tw_logm.begin(), plan.tw_logm.end(), l.logm) - plan.tw_logm.begin();
+        ChirpJob j{};
+        j.t = l.t;
+        j.logm = l.logm;
+        j.blue = l.blue ? 1 : 0;
+        j.chirp = l.blue ? ws + l.chirp_off : nullptr;
+        j.bhat = l.blue ? ws + l.bhat_off : nullptr;
+        j.roots = ws + l.roots_off;
+        j.tw_tab = ws + plan.tw_off[ti];
+        jobs[c] = j;
+    }
+}
+
+// Twiddle tables per FFT size, then the per-length set-up jobs, one launch
+// per size (the jobs are ordered by size).
+static hipError_t launch_fft_setup(const Plan &plan, uint8_t *ws, hipStream_t s, int &launches)
+{
+    const bool f64 = plan.mode == M_F64;
+    hipError_t e;
+    for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+        if ((e = launch_twiddles(f64, ws + plan.tw_off[c], plan.tw_logm[c], s)) != hipSuccess)
+            return e;
+        ++launches;
+    }
+    const ChirpJob *jobs = (const ChirpJob *)(ws + plan.job_off);
+    for (size_t c = 0; c < plan.lens.size();) {
+        size_t d = c;
+        while (d < plan.lens.size() && plan.lens[d].logm == plan.lens[c].logm)
+            ++d;
+        if ((e = launch_chirps(f64, plan.lens[c].logm, jobs + c, (int)(d - c), s)) != hipSuccess)
+            return e;
+        ++launches;
+        c = d;
+    }
+    return hipSuccess;
+}
+
 // Enqueues the whole forward path of a plan on stream s: one upload of the
 // device tables, the front end (normalisation of analytic input, or the FFT
 // analytic signal of real input), the Gram kernel and the epilogue.
@@ -330,46 +431,8 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             memcpy(blob.data() + plan.item_off, items.data(), items.size() * sizeof(Item));
             memcpy(blob.data() + plan.tile_off, tiles.data(), tiles.size() * sizeof(TileRef));
         }
-        if (real) {
-            const size_t nprob = plan.fft.size();
-            HilbertProb *hp = (HilbertProb *)(blob.data() + plan.hp_off);
-            BandBins *bins = (BandBins *)(blob.data() + plan.bin_off);
-            RowRef *rows = (RowRef *)(blob.data() + plan.row_off);
-            ChirpJob *jobs = (ChirpJob *)(blob.data() + plan.job_off);
-            for (size_t q = 0; q < nprob; ++q) {
-                const FftPlan &f = plan.fft[q];
-                const plv_problem &p = probs[q];
-                HilbertProb h{};
-                h.x = p.in;
-                h.ld = p.ld;
-                h.n = (int32_t)p.n;
-                h.t = f.t;
-                h.t0 = (int32_t)p.t0;
-                h.tw = plan.grams[q * nbands].t;
-                h.logm = f.logm;
-                h.blue = f.blue ? 1 : 0;
-                h.chirp = f.blue ? ws + plan.chirp_off[f.chirp_index] : nullptr;
-                h.bhat = f.blue ? ws + plan.bhat_off[f.chirp_index] : nullptr;
-                h.tw_tab = ws + plan.tw_off[f.tw_index];
-                h.gram0 = (int32_t)(q * nbands);
-                h.nbands = nbands;
-                h.bin0 = (int32_t)(q * nbands);
-                hp[q] = h;
-                for (int b = 0; b < nbands; ++b)
-                    bins[q * nbands + b] = band_bins(f.t, fs, bands ? &bands[b] : nullptr);
-            }
-            size_t r = 0;
-            for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
-                class_start.push_back((int)r);
-                for (size_t q = 0; q < nprob; ++q)
-                    if (plan.fft[q].logm == plan.tw_logm[c])
-                        for (int64_t i = 0; i < probs[q].n; ++i)
-                            rows[r++] = RowRef{(int32_t)q, (int32_t)i};
-                class_count.push_back((int)r - class_start.back());
-            }
-            for (size_t c = 0; c < plan.chirp_t.size(); ++c)
-                jobs[c] = ChirpJob{plan.chirp_t[c], plan.chirp_logm[c], ws + plan.chirp_off[c], ws + plan.bhat_off[c]};
-        }
+        if (real)
+            fill_fft_tables(plan, probs, nullptr, bands, nbands, fs, ws, blob, class_start, class_count);
         plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
         if (st != PLV_OK)
             return st;
@@ -378,18 +441,10 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
     hipError_t e;
     if (real) {
         StageTimer tm(ctx, PLV_STAGE_HILBERT, s);
-        const bool f64 = mode == M_F64;
-        for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
-            if ((e = launch_twiddles(f64, ws + plan.tw_off[c], plan.tw_logm[c], s)) != hipSuccess)
-                return hip_fail(ctx, e, "twiddle kernel launch");
-            tm.launched();
-        }
-        if (!plan.chirp_t.empty()) {
-            if ((e = launch_chirps(f64, (const ChirpJob *)(ws + plan.job_off), (int)plan.chirp_t.size(), s)) !=
-                hipSuccess)
-                return hip_fail(ctx, e, "chirp kernel launch");
-            tm.launched();
-        }
+        int nl = 0;
+        if ((e = launch_fft_setup(plan, ws, s, nl)) != hipSuccess)
+            return hip_fail(ctx, e, "FFT set-up kernel launch");
+        tm.launched(nl);
         for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
             HilbertArgs ha{};
             ha.hp = (const HilbertProb *)(ws + plan.hp_off);
@@ -398,8 +453,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             ha.nrows = class_count[c];
             ha.logm = plan.tw_logm[c];
             ha.gd = (const GramDesc *)(ws + plan.desc_off);
-            const int nwg = std::min(class_count[c], ctx->cus);
-            if ((e = launch_hilbert(mode, ha, nwg, s)) != hipSuccess)
+            if ((e = launch_hilbert(mode, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal kernel launch");
             tm.launched();
         }
@@ -521,47 +575,8 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
         memcpy(blob.data() + plan.desc_off, gd.data(), gd.size() * sizeof(GramDesc));
         if (plan.grouped)
             memcpy(blob.data() + plan.item_off, items.data(), items.size() * sizeof(Item));
-        if (real) {
-            const size_t nprob = plan.fft.size();
-            HilbertProb *hp = (HilbertProb *)(blob.data() + plan.hp_off);
-            BandBins *bins = (BandBins *)(blob.data() + plan.bin_off);
-            RowRef *rows = (RowRef *)(blob.data() + plan.row_off);
-            ChirpJob *jobs = (ChirpJob *)(blob.data() + plan.job_off);
-            for (size_t q = 0; q < nprob; ++q) {
-                const FftPlan &f = plan.fft[q];
-                const plv_problem &p = probs[q];
-                HilbertProb h{};
-                h.x = p.in;
-                h.ld = p.ld;
-                h.n = (int32_t)p.n;
-                h.t = f.t;
-                h.t0 = (int32_t)p.t0;
-                h.tw = plan.grams[q * nbands].t;
-                h.logm = f.logm;
-                h.blue = f.blue ? 1 : 0;
-                h.chirp = f.blue ? ws + plan.chirp_off[f.chirp_index] : nullptr;
-                h.bhat = f.blue ? ws + plan.bhat_off[f.chirp_index] : nullptr;
-                h.tw_tab = ws + plan.tw_off[f.tw_index];
-                h.gram0 = (int32_t)(q * nbands);
-                h.nbands = nbands;
-                h.bin0 = (int32_t)(q * nbands);
-                h.xbar = grads[q].din;
-                hp[q] = h;
-                for (int b = 0; b < nbands; ++b)
-                    bins[q * nbands + b] = band_bins(f.t, fs, bands ? &bands[b] : nullptr);
-            }
-            size_t r = 0;
-            for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
-                class_start.push_back((int)r);
-                for (size_t q = 0; q < nprob; ++q)
-                    if (plan.fft[q].logm == plan.tw_logm[c])
-                        for (int64_t i = 0; i < probs[q].n; ++i)
-                            rows[r++] = RowRef{(int32_t)q, (int32_t)i};
-                class_count.push_back((int)r - class_start.back());
-            }
-            for (size_t c = 0; c < plan.chirp_t.size(); ++c)
-                jobs[c] = ChirpJob{plan.chirp_t[c], plan.chirp_logm[c], ws + plan.chirp_off[c], ws + plan.bhat_off[c]};
-        }
+        if (real)
+            fill_fft_tables(plan, probs, grads, bands, nbands, fs, ws, blob, class_start, class_count);
         plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
         if (st != PLV_OK)
             return st;
@@ -575,20 +590,18 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
     ha.gd = (const GramDesc *)(ws + plan.desc_off);
     if (real) {
         // analytic signal of the window, kept unnormalised in zbuf
-        for (size_t c = 0; c < plan.tw_logm.size(); ++c)
-            if ((e = launch_twiddles(f64, ws + plan.tw_off[c], plan.tw_logm[c], s)) != hipSuccess)
-                return hip_fail(ctx, e, "twiddle kernel launch");
-        if (!plan.chirp_t.empty() &&
-            (e = launch_chirps(f64, (const ChirpJob *)(ws + plan.job_off), (int)plan.chirp_t.size(), s)) != hipSuccess)
-            return hip_fail(ctx, e, "chirp kernel launch");
+        int nl = 0;
+        if ((e = launch_fft_setup(plan, ws, s, nl)) != hipSuccess)
+            return hip_fail(ctx, e, "FFT set-up kernel launch");
         for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
             ha.rows = (const RowRef *)(ws + plan.row_off) + class_start[c];
             ha.nrows = class_count[c];
             ha.logm = plan.tw_logm[c];
-            if ((e = launch_hilbert(mode, ha, std::min(class_count[c], ctx->cus), s)) != hipSuccess)
+            if ((e = launch_hilbert(mode, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal kernel launch");
+            ++nl;
         }
-        tm.launched(3);
+        tm.launched(nl);
     }
     // operands of ubar = H (conj U^T)^H
     for (size_t q = 0; q < plan.grams.size(); ++q) {
@@ -674,7 +687,7 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
             ha.rows = (const RowRef *)(ws + plan.row_off) + class_start[c];
             ha.nrows = class_count[c];
             ha.logm = plan.tw_logm[c];
-            if ((e = launch_hilbert_adjoint(f64, ha, std::min(class_count[c], ctx->cus), s)) != hipSuccess)
+            if ((e = launch_hilbert_adjoint(f64, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal adjoint kernel launch");
             tm.launched();
         }

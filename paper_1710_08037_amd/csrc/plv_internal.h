@@ -124,6 +124,7 @@ struct HilbertProb {
     const void *chirp;   // [t] complex c_m = exp(i pi m^2 / t) (Bluestein)
     const void *bhat;    // [M] complex FFT_M of the circular chirp (Bluestein)
     const void *tw_tab;  // [M/2] complex exp(-2 pi i k / M)
+    const void *roots;   // [t] complex exp(2 pi i m / t) (direct band synthesis)
     int32_t gram0;       // Gram problem of band 0 (band b -> gram0 + b)
     int32_t nbands;
     int32_t bin0;        // first entry of this problem in the band-bin table
@@ -133,8 +134,10 @@ struct HilbertProb {
 
 // Positive-frequency bins [klo, khi] that get weight 2; klo < 0 selects the
 // plain one-sided weights (1 at DC, 2 below Nyquist, 1 at Nyquist, 0 above).
+// direct = 1: synthesise the band from its bins instead of an inverse FFT.
 struct BandBins {
     int32_t klo, khi;
+    int32_t direct, pad_;
 };
 
 struct RowRef {
@@ -150,11 +153,15 @@ struct HilbertArgs {
     const GramDesc *gd;   // destinations of the phasor planes
 };
 
-// Bluestein set-up for one distinct length t.
+// Set-up for one distinct row length t: its root table, and for a Bluestein
+// length the chirp and the transformed circular chirp.
 struct ChirpJob {
     int32_t t, logm;
-    void *chirp;          // [t] complex
-    void *bhat;           // [M] complex (written as the circular chirp, then transformed in place)
+    int32_t blue, pad_;
+    void *chirp;          // [t] complex (Bluestein)
+    void *bhat;           // [M] complex (Bluestein)
+    void *roots;          // [t] complex
+    const void *tw_tab;   // [M/2] twiddles of this M
 };
 
 // ---------------------------------------------------------------- backward --
@@ -196,9 +203,12 @@ int herk_occupancy(int mode);
 constexpr int FFT_MAXLOG_F32 = 13;  // M <= 8192 complex FP32 transforms in LDS
 constexpr int FFT_MAXLOG_F64 = 12;  // M <= 4096 complex FP64
 hipError_t launch_twiddles(bool f64, void *tab, int logm, hipStream_t s);
-hipError_t launch_chirps(bool f64, const ChirpJob *jobs, int njobs, hipStream_t s);
-hipError_t launch_hilbert(int mode, const HilbertArgs &a, int nwg, hipStream_t s);
-hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int nwg, hipStream_t s);
+// jobs: device array of njobs set-ups that all have this logm
+hipError_t launch_chirps(bool f64, int logm, const ChirpJob *jobs, int njobs, hipStream_t s);
+// rows of a.rows all have FFT size a.logm; the grid is sized from cus and the
+// kernel's occupancy
+hipError_t launch_hilbert(int mode, const HilbertArgs &a, int cus, hipStream_t s);
+hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int cus, hipStream_t s);
 hipError_t launch_planes_t(int mode, const BwdPlanesArgs &a, hipStream_t s);
 hipError_t launch_metric_adjoint(int mode, const BwdMetricArgs &a, hipStream_t s);
 hipError_t launch_normalise_adjoint(bool f64, const BwdNormArgs &a, hipStream_t s);

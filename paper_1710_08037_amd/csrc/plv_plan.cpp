@@ -245,16 +245,24 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
             f.tw_index = (int)(it - plan.tw_logm.begin());
             if (it == plan.tw_logm.end())
                 plan.tw_logm.push_back(f.logm);
-            if (f.blue) {
-                auto jt = std::find(plan.chirp_t.begin(), plan.chirp_t.end(), f.t);
-                f.chirp_index = (int)(jt - plan.chirp_t.begin());
-                if (jt == plan.chirp_t.end()) {
-                    plan.chirp_t.push_back(f.t);
-                    plan.chirp_logm.push_back(f.logm);
-                }
+            bool seen = false;
+            for (const LenPlan &l : plan.lens)
+                seen = seen || l.t == f.t;
+            if (!seen) {
+                LenPlan l;
+                l.t = f.t;
+                l.logm = f.logm;
+                l.blue = f.blue;
+                plan.lens.push_back(l);
             }
             plan.nrows += (size_t)probs[q].n;
         }
+        std::sort(plan.lens.begin(), plan.lens.end(),
+                  [](const LenPlan &a, const LenPlan &b) { return a.logm != b.logm ? a.logm < b.logm : a.t < b.t; });
+        for (FftPlan &f : plan.fft)
+            for (size_t c = 0; c < plan.lens.size(); ++c)
+                if (plan.lens[c].t == f.t)
+                    f.len_index = (int)c;
         plan.hp_off = off;
         off += align256((size_t)nprob * sizeof(HilbertProb));
         plan.bin_off = off;
@@ -262,17 +270,21 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         plan.row_off = off;
         off += align256(plan.nrows * sizeof(RowRef));
         plan.job_off = off;
-        off += align256(plan.chirp_t.size() * sizeof(ChirpJob));
+        off += align256(plan.lens.size() * sizeof(ChirpJob));
         plan.tables_bytes = off;
         for (int lg : plan.tw_logm) {
             plan.tw_off.push_back(off);
             off += align256((size_t)(1 << lg) / 2 * csz);
         }
-        for (size_t c = 0; c < plan.chirp_t.size(); ++c) {
-            plan.chirp_off.push_back(off);
-            off += align256((size_t)plan.chirp_t[c] * csz);
-            plan.bhat_off.push_back(off);
-            off += align256((size_t)(1 << plan.chirp_logm[c]) * csz);
+        for (LenPlan &l : plan.lens) {
+            l.roots_off = off;
+            off += align256((size_t)l.t * csz);
+            if (l.blue) {
+                l.chirp_off = off;
+                off += align256((size_t)l.t * csz);
+                l.bhat_off = off;
+                off += align256((size_t)(1 << l.logm) * csz);
+            }
         }
     } else {
         plan.tables_bytes = off;

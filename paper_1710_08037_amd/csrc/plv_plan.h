@@ -38,7 +38,14 @@ struct FftPlan {
     int t = 0, logm = 0;
     bool blue = false;
     int tw_index = 0;     // which twiddle table (by logm)
-    int chirp_index = -1; // which Bluestein set-up (by t), or -1
+    int len_index = 0;    // which per-length set-up (by t)
+};
+
+// Set-up tables of one distinct row length.
+struct LenPlan {
+    int t = 0, logm = 0;
+    bool blue = false;
+    size_t roots_off = 0, chirp_off = 0, bhat_off = 0;  // chirp/bhat: Bluestein only
 };
 
 struct Plan {
@@ -53,8 +60,7 @@ struct Plan {
     std::vector<FftPlan> fft;                 // per problem
     std::vector<int> tw_logm;                 // distinct FFT sizes
     std::vector<size_t> tw_off;
-    std::vector<int> chirp_t, chirp_logm;     // distinct Bluestein lengths
-    std::vector<size_t> chirp_off, bhat_off;
+    std::vector<LenPlan> lens;                // distinct row lengths, ordered by (logm, t)
     size_t hp_off = 0, bin_off = 0, row_off = 0, job_off = 0;
     size_t nrows = 0;
     size_t total = 0;

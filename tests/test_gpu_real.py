@@ -72,7 +72,10 @@ def test_bluestein_and_radix2_lengths(prec, t):
 @pytest.mark.parametrize("t", [2000, 2048, 3001])
 def test_bands_and_window(prec, t):
     n, fs = 23, 1000.0
-    bands = [(8.0, 12.0), (0.0, 0.0), (18.0, 22.0), (10.0, 10.0)]
+    # narrow bands (synthesised from their bins where that is cheaper), the
+    # plain analytic signal, a single-frequency band and a wide band (inverse
+    # transform)
+    bands = [(8.0, 12.0), (0.0, 0.0), (18.0, 22.0), (10.0, 10.0), (5.0, 200.0)]
     x = synth.glag_real(n, t, fs, 4, (8, 22), seed=400 + t)
     win = (150, t - 170)
     if not fits_lds_fft(t, prec):
