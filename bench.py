@@ -18,7 +18,9 @@ conventions): ``small`` N = 64 real f64 signals, T = 2048 at 256 Hz, FP64
 end to end; ``batch`` 512 trials of uneven N in {68, 148, 360, 1000} and T in
 [500, 4000] at 1 kHz, five 4 Hz bands each, real f32, FFT analytic signal and
 one grouped Gram launch; ``grad`` N = 2048 real f32 signals, T = 8192,
-forward plus adjoint of the ciPLV target loss.
+forward plus adjoint of the ciPLV target loss; ``brain`` N = 15000 unit
+phasors, T = 1.2e6 (144 GB of complex64 made on the GPU), 200 planted lagged
+pairs, 16-bit MFMA with FP64 sums across K-chunks.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -236,6 +238,97 @@ def bench_grad(args):
                     args, "bf16", {"n": n, "t": t, "prec": args.prec_batch}, {"stage_ms": stages})
 
 
+def bench_brain(args):
+    """Whole-brain scale: N = 15000 unit phasors of T = 1.2e6 samples (144 GB
+    of complex64, generated on the GPU), 200 planted constant-lag pairs;
+    16-bit MFMA with FP32 accumulation in K-chunks and FP64 sums across them."""
+    import numpy as np
+    import torch
+
+    import paper_1710_08037_amd as plv
+    from synth import seed_for
+    from synth.device import phasors_planted_device
+
+    n, t, npairs = 15000, 1200000, 200
+    prec = args.prec_brain
+    z, pairs, lags = phasors_planted_device(n, t, npairs, seed_for(3))
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 3))
+    warm = max(1, min(args.warmup, 1))
+    box = {}
+
+    def step():
+        box["out"] = plv.from_analytic(z, prec=prec, want=("plv", "iplv", "ciplv"))
+
+    ms, stages = timed(step, steps, warm)
+    ps = n * (n - 1) // 2 * t
+    extra = {"stage_ms": stages, "pair_samples": ps}
+    if stages.get("gram"):
+        flops = FLOP_PER_PAIR_SAMPLE[prec] * ps
+        extra["gram_tflops"] = round(flops / (stages["gram"] / 1e3) / 1e12, 1)
+        extra["gram_frac_of_peak"] = round(flops / (stages["gram"] / 1e3) / 1e12 / PEAK_TFLOPS[prec], 4)
+    if not args.no_cpu:
+        extra["cpu_baseline"], extra["max_abs_err"] = brain_cpu_leg(z, pairs, box["out"])
+    extra["steps_note"] = "at most 3 timed steps of about a second each"
+    line = line_for("whole-brain: N=15000 unit phasors x T=1.2e6 (complex64, generated on the GPU), "
+                    "200 planted lagged pairs", ps / (ms / 1e3), ms, args, prec, {"n": n, "t": t, "prec": prec},
+                    extra)
+    line["steps"] = steps
+    line["warmup"] = warm
+    return line
+
+
+def brain_cpu_leg(z, pairs, out, budget_s=15.0):
+    """The oracle on the planted pairs plus all pairs among R random other
+    rows (R sized for about `budget_s`), timed, and the GPU results checked
+    on exactly those pairs."""
+    import numpy as np
+
+    import oracle
+
+    n, t = z.shape
+    nthreads = oracle.threads()
+    rng = np.random.default_rng(5)
+    planted = np.unique(pairs.reshape(-1))
+    rest = np.setdiff1d(np.arange(n), planted)
+    probe = 16
+    rows = np.sort(rng.choice(rest, size=probe, replace=False))
+    zz = z[rows].cpu().numpy().astype(np.complex128)
+    pr = oracle.upper_pairs(probe)
+    t0 = time.perf_counter()
+    oracle.pair_means(oracle.phase(zz), pr, nthreads)
+    rate = len(pr) * t / (time.perf_counter() - t0)
+    r = int(max(probe, math.sqrt(2 * max(rate * budget_s / t - len(pairs), 0))))
+    rows = np.sort(np.concatenate([planted, rng.choice(rest, size=r, replace=False)]))
+    zz = z[rows].cpu().numpy().astype(np.complex128)
+    pos = {int(v): k for k, v in enumerate(rows)}
+    rnd = np.array([pos[int(v)] for v in rows if int(v) not in set(planted.tolist())])
+    loc = np.array([[pos[int(a)], pos[int(b)]] for a, b in pairs], dtype=np.int64)
+    ii, jj = np.triu_indices(len(rnd), 1)
+    loc = np.concatenate([loc, np.stack([rnd[ii], rnd[jj]], 1)])
+    loc = np.stack([loc.min(1), loc.max(1)], 1)
+    t0 = time.perf_counter()
+    g = oracle.pair_means(oracle.phase(zz), loc, nthreads)
+    dt = time.perf_counter() - t0
+    p, ip, cp = oracle.metrics(g)
+    a = rows[loc[:, 0]]
+    b = rows[loc[:, 1]]
+    errs = {}
+    ia, ib = torch_index(a), torch_index(b)
+    for k, ref in (("plv", p), ("iplv", ip), ("ciplv", cp)):
+        got = out[k][ia, ib].cpu().numpy().astype(np.float64)
+        errs[k] = float(np.abs(got - ref).max())
+    base = {"value": round(len(loc) * t / dt, 1), "unit": "pair-samples/s", "cores": nthreads, "kind": "oracle",
+            "sample": "the %d planted pairs and all %d pairs among %d other random signals, x %d samples, %.1f s"
+                      % (len(pairs), len(loc) - len(pairs), len(rnd), t, dt)}
+    return base, errs
+
+
+def torch_index(a):
+    import torch
+    return torch.from_numpy(a).cuda()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,8 +339,9 @@ def main():
                     help="paths to time (both: split-BF16 for `value`, FP32 beside it)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 3 times (counter calibration) and exit")
-    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad"])
+    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain"])
     ap.add_argument("--prec-batch", default="split_bf16", help="precision of the batch and grad workloads")
+    ap.add_argument("--prec-brain", default="bf16", choices=["bf16", "f16"], help="precision of the brain workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X (use --gpus 1)", file=sys.stderr)
@@ -268,7 +362,7 @@ def main():
         print(json.dumps({"copy_ref_bytes": args.copy_ref}), flush=True)
         return
     if args.workload != "sensor":
-        fn = {"small": bench_small, "batch": bench_batch, "grad": bench_grad}[args.workload]
+        fn = {"small": bench_small, "batch": bench_batch, "grad": bench_grad, "brain": bench_brain}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     z_np = synth.glag_analytic(N_SIG, T_SAMP, FS, 32, (8.0, 12.0), seed=synth.seed_for(2), dtype=np.complex64)

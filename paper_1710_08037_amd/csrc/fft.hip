@@ -389,7 +389,6 @@ __device__ inline void store_band(int mode, const GramDesc &g, const HilbertProb
             gst(zr, s, zf(hp.t0 + s));
         return;
     }
-    uint8_t *urow = (uint8_t *)g.u + (int64_t)row * g.ldu * cbytes_of(mode);
     for (int s0 = threadIdx.x * 4; s0 < g.tpad; s0 += nt * 4) {
         R ur[4], ui[4];
 #pragma unroll
@@ -402,7 +401,8 @@ __device__ inline void store_band(int mode, const GramDesc &g, const HilbertProb
                 unit_phasor(z.x, z.y, ur[v], ui[v]);
             }
         }
-        store4_mode<R>(mode, urow + (int64_t)s0 * cbytes_of(mode), g.plane_bytes, ur, ui);
+        store4_mode<R>(mode, plane_at((uint8_t *)g.u, g.cstride, (int)g.ldu, cbytes_of(mode), row, s0),
+                       g.plane_bytes, ur, ui);
     }
 }
 
@@ -426,7 +426,6 @@ __device__ inline void direct_band(int mode, const GramDesc &g, const HilbertPro
     const int step = (int)(((int64_t)kl * 4 * nt) % t);
     const int limit = g.zbuf ? hp.tw : g.tpad;
     cx<R> *zrow = (cx<R> *)g.zbuf + (int64_t)row * g.ldz;
-    uint8_t *urow = (uint8_t *)g.u + (int64_t)row * g.ldu * cbytes_of(mode);
     for (int s0 = s_first; s0 < limit; s0 += nt * 4) {
         cx<R> w[4], acc[4], base[4];
         int ix = idx;
@@ -465,7 +464,8 @@ __device__ inline void direct_band(int mode, const GramDesc &g, const HilbertPro
                 if (s0 + v < hp.tw)
                     unit_phasor(z[v].x, z[v].y, ur[v], ui[v]);
             }
-            store4_mode<R>(mode, urow + (int64_t)s0 * cbytes_of(mode), g.plane_bytes, ur, ui);
+            store4_mode<R>(mode, plane_at((uint8_t *)g.u, g.cstride, (int)g.ldu, cbytes_of(mode), row, s0),
+                           g.plane_bytes, ur, ui);
         }
     }
 }

@@ -143,7 +143,7 @@ constexpr int WAVES = 8;   // two groups of four waves per work-group
 constexpr int THREADS = 64 * WAVES;
 
 template <int MODE, bool DIAG>
-__device__ inline void herk_tile(const GramDesc &d, int I, int J, int k0, int nst,
+__device__ inline void herk_tile(const GramDesc &d, const uint8_t *ua, const uint8_t *ub, int I, int J, int nst,
                                  typename AccOf<MODE>::type (&re)[tile_of(MODE) / 32][tile_of(MODE) / 32],
                                  typename AccOf<MODE>::type (&im)[tile_of(MODE) / 32][tile_of(MODE) / 32],
                                  uint8_t *smem)
@@ -167,8 +167,8 @@ __device__ inline void herk_tile(const GramDesc &d, int I, int J, int k0, int ns
     const int64_t pitch = d.ldu * CB;
     const int lr = lane >> 2;
     const uint32_t voff = (uint32_t)(lr * pitch) + (uint32_t)(((lane & 3) ^ swz(lr)) * 16);
-    const uint8_t *gA = d.u + (int64_t)I * BM * pitch + (int64_t)k0 * CB;
-    const uint8_t *gB = (d.ub ? d.ub : d.u) + (int64_t)J * BM * pitch + (int64_t)k0 * CB;
+    const uint8_t *gA = ua + (int64_t)I * BM * pitch;
+    const uint8_t *gB = ub + (int64_t)J * BM * pitch;
     auto issue = [&](int st, int buf) {
         const int64_t koff = (int64_t)st * RB;
         uint8_t *base = smem + buf * STAGE;
@@ -360,6 +360,10 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
     if (d.ub) {  // general product: full grid, row-major over (I, J)
         I = tile / d.ntile_b;
         J = tile - I * d.ntile_b;
+    } else if (args.order) {  // blocked launch order of a single problem
+        const int v = args.order[tile];
+        I = v >> 16;
+        J = v & 0xffff;
     } else {
         tile_ij(tile, d.ntile, I, J);
     }
@@ -375,10 +379,13 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
             re[a][b] = acc_t{0, 0, 0, 0};
             im[a][b] = acc_t{0, 0, 0, 0};
         }
+    // the chunk's block of the planes (one block, cstride 0, in product mode)
+    const uint8_t *ua = d.u + (int64_t)chunk * d.cstride;
+    const uint8_t *ub = (d.ub ? d.ub : d.u) + (int64_t)chunk * d.cstride;
     if (I == J && !d.ub)
-        herk_tile<MODE, true>(d, I, J, k0, nst, re, im, smem);
+        herk_tile<MODE, true>(d, ua, ub, I, J, nst, re, im, smem);
     else
-        herk_tile<MODE, false>(d, I, J, k0, nst, re, im, smem);
+        herk_tile<MODE, false>(d, ua, ub, I, J, nst, re, im, smem);
     fold_groups<MODE>(re, im, smem);
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -434,7 +441,10 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
     // Accumulator layout of a 16x16 block: lane l, register r holds column
     // l % 16 of row 4 (l / 16) + r for the FP32-output MFMAs, and of row
     // l / 16 + 4 r for v_mfma_f64_16x16x4f64.
-    auto out = gptr(d.partial + ((int64_t)slot * d.nupper + tile) * 2 * BM * BM);
+    // Slots are indexed by the row-major upper-triangle index of (I, J),
+    // which the epilogue decodes, whatever order the tiles were launched in.
+    const int tile_rm = I * d.ntile - I * (I - 1) / 2 + (J - I);
+    auto out = gptr(d.partial + ((int64_t)slot * d.nupper + tile_rm) * 2 * BM * BM);
     const int r0 = wm * (BM / 2) + (MODE == M_F64 ? (lane >> 4) : (lane >> 4) * 4);
     constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;
     const int c0 = wn * (BM / 2) + (lane & 15);

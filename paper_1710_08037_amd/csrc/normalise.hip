@@ -24,7 +24,7 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
     const int s0 = (blockIdx.x * 256 + threadIdx.x) * VEC;
     if (s0 >= a.tpad)
         return;
-    uint8_t *dst = a.u + ((int64_t)row * a.ldu + s0) * cbytes_of(MODE);
+    uint8_t *dst = plane_at(a.u, a.cstride, a.chunk, cbytes_of(MODE), row, s0);  // 4 samples never straddle chunks
     typedef typename std::conditional<MODE == M_F64, double, float>::type real_t;
     typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
     auto src = gptr((const cplx_t *)a.in + (int64_t)row * a.ld + a.t0);

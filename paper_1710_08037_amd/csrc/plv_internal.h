@@ -1,11 +1,14 @@
 // plv_internal.h -- descriptors shared by the host layer and the gfx950 kernels.
 //
 // Layout of the phasor planes U in the workspace (one "Gram problem" = one
-// problem x band):
-//   rows [npad][ldu] of interleaved complex phasors u = z/|z| (Eq. 4), T-contiguous;
-//   ldu = tpad = window length rounded up to PLV_KGRAN samples, zero-filled
-//   beyond the window (padding adds nothing to G); rows n..npad-1 are never
-//   written and only feed output entries that are discarded.
+// problem x band): chunk-major.  The window, rounded up to tpad (a multiple
+// of PLV_KGRAN samples, zero-filled beyond the window: padding adds nothing to
+// G), is cut into K-chunks of `chunk` samples; chunk c of every row is stored
+// together as a block [npad][chunk] of interleaved complex phasors
+// u = z/|z| (Eq. 4), blocks cstride bytes apart.  A Gram work-group reads one
+// block, so its rows sit a chunk apart rather than a whole T apart (few pages
+// per panel).  Rows n..npad-1 are never written and only feed output entries
+// that are discarded; the tail of the last block past tpad is never touched.
 //   Element per complex sample: 2 x bf16/f16 (4 B), 2 x f32 (8 B), 2 x f64 (16 B).
 //   PLV_PREC_SPLIT_BF16 has two such planes, hi then lo, plane_bytes apart.
 #pragma once
@@ -43,6 +46,14 @@ typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
 
 enum Mode { M_F64 = 0, M_F32 = 1, M_SPLIT = 2, M_BF16 = 3, M_F16 = 4 };
 
+// Address of sample s of `row` in chunk-major phasor planes (plane 0);
+// cb bytes per complex element.
+__device__ inline uint8_t *plane_at(uint8_t *u, int64_t cstride, int chunk, int cb, int64_t row, int s)
+{
+    const int c = s / chunk;
+    return u + c * cstride + (row * chunk + (s - c * chunk)) * cb;
+}
+
 // Tile edge of the Gram kernel for each mode (output tiles are BM x BM).
 __host__ __device__ constexpr int tile_of(int mode) { return mode == M_F64 ? 64 : 128; }
 // Bytes per complex phasor element in one plane.
@@ -53,7 +64,8 @@ __host__ __device__ constexpr int planes_of(int mode) { return mode == M_SPLIT ?
 struct GramDesc {
     const uint8_t *u;     // plane 0
     int64_t plane_bytes;  // plane 1 = u + plane_bytes (split only)
-    int64_t ldu;          // row pitch of U in complex elements (= tpad)
+    int64_t ldu;          // row pitch of U in complex elements (= chunk)
+    int64_t cstride;      // bytes from one chunk block to the next (0: one block)
     int32_t n, npad;      // signals, rows rounded up to the tile
     int32_t t, tpad;      // true window length (the 1/T), padded length
     int32_t ntile;        // tiles per side = npad / BM
@@ -91,6 +103,7 @@ struct HerkArgs {
     const Item *items;      // work items (grouped launch: `chunk` is the slot), or nullptr
     int32_t nitems;
     int32_t pass;           // chunk = pass * nslot + slot; pass > 0 adds into the slot
+    const int32_t *order;   // single Gram problem: tile position -> I << 16 | J, or nullptr
 };
 
 struct EpiArgs {
@@ -108,7 +121,8 @@ struct NormArgs {
     int32_t n;            // rows
     uint8_t *u;           // plane 0
     int64_t plane_bytes;
-    int64_t ldu;          // = tpad
+    int64_t cstride;      // chunk-major layout of the planes (see above)
+    int32_t chunk;
     int32_t tpad;
 };
 

@@ -196,3 +196,21 @@ def test_sensor_scale_workload_sampled_pairs(prec):
     lhs = np.vdot(w, got["g"] @ w).real
     rhs = np.linalg.norm(u.conj().T @ w) ** 2 / t
     assert abs(lhs - rhs) <= tol * np.abs(w).sum() ** 2
+
+
+@pytest.mark.parametrize("prec", ["f32", "split_bf16", "f64"])
+def test_many_tiles_many_chunks_sampled_pairs(prec):
+    """N = 2000 signals (16 tiles a side, 8 for FP64's smaller tiles: the
+    launch order of the tiles is blocked, not row-major) over T = 40000
+    samples (several K-chunks, so chunk sums go through the partial slots and
+    the epilogue): every pair among 40 sampled rows, which land in many
+    different tiles, against the oracle."""
+    n, t = 2000, 40000
+    z = synth.uniform_phasors(n, t, seed=synth.seed_for(2, 7), dtype=np.complex64)
+    lagged = synth.glag_analytic(200, t, 1000.0, 8, (8.0, 12.0), seed=synth.seed_for(2, 8), dtype=np.complex64)
+    z[::10] = lagged  # some structure spread over all tiles
+    got = gpu_full(z, prec)
+    rows = np.sort(np.random.default_rng(9).choice(n, size=40, replace=False))
+    ref = oracle.full_from_analytic(exact_input(z[rows], prec))
+    sub = {k: v[np.ix_(rows, rows)] for k, v in got.items()}
+    compare(sub, ref, TOL[prec], "N=2000 T=40000 %s" % prec)
