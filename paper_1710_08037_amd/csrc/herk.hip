@@ -347,6 +347,8 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
     int tile, slot;
     if (args.items) {
         const Item it = args.items[item];
+        if (it.gram < 0)
+            return;  // padding of an XCD's list
         d = args.gd[it.gram];
         tile = it.tile;
         slot = it.chunk;

@@ -100,7 +100,7 @@ struct TileRef {
 struct HerkArgs {
     GramDesc g;             // the single problem when items == nullptr
     const GramDesc *gd;     // problem table (grouped launch)
-    const Item *items;      // work items (grouped launch: `chunk` is the slot), or nullptr
+    const Item *items;      // work items (grouped launch: `chunk` is the slot; gram < 0: none), or nullptr
     int32_t nitems;
     int32_t pass;           // chunk = pass * nslot + slot; pass > 0 adds into the slot
     const int32_t *order;   // single Gram problem: tile position -> I << 16 | J, or nullptr

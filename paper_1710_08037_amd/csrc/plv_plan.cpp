@@ -62,6 +62,60 @@ void choose_chunks_grouped(GramPlan &g)
     g.nslot = g.nchunk;
 }
 
+// Grouped launches: whole problems go to XCDs by longest-processing-time
+// bin packing on their estimated cost, and each XCD's list keeps a problem's
+// items together (its tiles share panels in that XCD's L2), most costly
+// problems first.  The lists are padded with empty items (gram = -1) to one
+// length and stored XCD after XCD, matching the kernel's remap of work-group
+// ids (XCD x = id mod 8 runs entries x * len .. x * len + len - 1 in order).
+// A plain longest-first order of items would hand XCD 0 all the longest ones.
+constexpr int NXCD = 8;
+constexpr double ITEM_OVERHEAD = 512.0;  // fixed cost of an item, in samples of K
+
+void schedule_items(Plan &plan)
+{
+    const size_t np = plan.grams.size();
+    std::vector<std::pair<double, size_t>> cost(np);
+    for (size_t q = 0; q < np; ++q) {
+        const GramPlan &g = plan.grams[q];
+        double c = 0.0;
+        for (int k = 0; k < g.nchunk; ++k)  // product mode (backward): K = kpad
+            c += (g.kpad > 0 ? g.kpad : std::min(g.chunk, g.tpad - k * g.chunk)) + ITEM_OVERHEAD;
+        cost[q] = {c * g.nupper, q};
+    }
+    std::stable_sort(cost.begin(), cost.end(),
+                     [](const std::pair<double, size_t> &a, const std::pair<double, size_t> &b) {
+                         return a.first > b.first;
+                     });
+    double load[NXCD] = {};
+    size_t count[NXCD] = {};
+    std::vector<size_t> lists[NXCD];
+    for (const auto &pc : cost) {
+        int x = 0;
+        for (int y = 1; y < NXCD; ++y)
+            if (load[y] < load[x])
+                x = y;
+        load[x] += pc.first;
+        const GramPlan &g = plan.grams[pc.second];
+        count[x] += (size_t)g.nupper * g.nchunk;
+        lists[x].push_back(pc.second);
+    }
+    size_t len = 0;
+    for (int x = 0; x < NXCD; ++x)
+        len = std::max(len, count[x]);
+    plan.items.assign(len * NXCD, Item{-1, 0, 0, 0});
+    for (int x = 0; x < NXCD; ++x) {
+        size_t k = (size_t)x * len;
+        for (size_t q : lists[x]) {
+            const GramPlan &g = plan.grams[q];
+            for (int c = 0; c < g.nchunk; ++c)
+                for (int t = 0; t < g.nupper; ++t)
+                    plan.items[k++] = Item{(int32_t)q, t, c, 0};
+        }
+    }
+    plan.nitems = plan.items.size();
+}
+
 }  // namespace
 
 plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
@@ -193,8 +247,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
             g.nslot = 1;
         }
         if (grouped) {
-            for (const GramPlan &g : plan.grams)
-                plan.nitems += (size_t)g.nupper;
+            schedule_items(plan);
             if (plan.nitems > (size_t)INT32_MAX) {
                 why = "too many work items";
                 return PLV_ERR_INVALID_ARG;
@@ -207,11 +260,10 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
             choose_chunks_grouped(g);
             g.fused = g.nchunk == 1;
         }
-        for (const GramPlan &g : plan.grams) {
-            plan.nitems += (size_t)g.nupper * g.nchunk;
+        schedule_items(plan);
+        for (const GramPlan &g : plan.grams)
             if (!g.fused)
                 plan.ntiles += (size_t)g.nupper;
-        }
         if (plan.nitems > (size_t)INT32_MAX || plan.ntiles > (size_t)INT32_MAX) {
             why = "too many work items";
             return PLV_ERR_INVALID_ARG;
@@ -391,26 +443,16 @@ void blocked_order(int ntile, std::vector<int32_t> &order)
 void build_tables(const Plan &plan, const std::vector<GramDesc> &gd, std::vector<Item> &items,
                   std::vector<TileRef> &tiles)
 {
-    items.clear();
+    items = plan.items;
     tiles.clear();
-    items.reserve(plan.nitems);
     tiles.reserve(plan.ntiles);
     const bool backward = plan.op == PLV_OP_BACKWARD_ANALYTIC || plan.op == PLV_OP_BACKWARD_REAL;
     for (size_t q = 0; q < gd.size(); ++q) {
         const GramDesc &d = gd[q];
-        for (int c = 0; c < d.nchunk; ++c)
-            for (int t = 0; t < d.nupper; ++t)
-                items.push_back(Item{(int32_t)q, t, c, 0});
         if (!backward && !d.fused)
             for (int t = 0; t < d.nupper; ++t)
                 tiles.push_back(TileRef{(int32_t)q, t});
     }
-    // longest items first, so the tail of the launch is short work
-    auto cost = [&](const Item &it) {
-        const GramDesc &d = gd[it.gram];
-        return std::min(d.chunk, d.tpad - it.chunk * d.chunk);
-    };
-    std::stable_sort(items.begin(), items.end(), [&](const Item &a, const Item &b) { return cost(a) > cost(b); });
 }
 
 }  // namespace plv

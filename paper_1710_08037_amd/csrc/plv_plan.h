@@ -57,6 +57,7 @@ struct Plan {
     size_t order_off = 0;                     // single Gram problem: blocked tile order
     bool has_order = false;
     size_t nitems = 0, ntiles = 0;
+    std::vector<Item> items;                  // grouped launch: work items, XCD-major (see schedule_items)
     bool grouped = false;                     // Gram work from the item table
     // real input only
     std::vector<FftPlan> fft;                 // per problem
