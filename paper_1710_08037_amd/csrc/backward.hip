@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void metric_adjoint_kernel(BwdMetricArgs a)
 {
     typedef typename std::conditional<MODE == M_F64, double, float>::type R;
     typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
-    const int64_t i = blockIdx.y;
+    const int64_t i = a.row0 + blockIdx.y;
     const int j0 = (blockIdx.x * 256 + threadIdx.x) * 4;
     if (j0 >= a.kpad)
         return;
@@ -119,7 +119,7 @@ template <class R>
 __global__ __launch_bounds__(256) void normalise_adjoint_kernel(BwdNormArgs a)
 {
     typedef typename std::conditional<sizeof(R) == 8, vd2, vf2>::type cplx_t;
-    const int64_t row = blockIdx.y;
+    const int64_t row = a.row0 + blockIdx.y;
     const int q = blockIdx.x * 256 + threadIdx.x;  // position in the output row
     if (q >= a.len)
         return;
@@ -163,24 +163,38 @@ hipError_t launch_planes_t(int mode, const BwdPlanesArgs &a, hipStream_t s)
 
 hipError_t launch_metric_adjoint(int mode, const BwdMetricArgs &a, hipStream_t s)
 {
-    dim3 grid((a.kpad / 4 + 255) / 256, a.n);
-    switch (mode) {
-    case M_F64: metric_adjoint_kernel<M_F64><<<grid, 256, 0, s>>>(a); break;
-    case M_F32: metric_adjoint_kernel<M_F32><<<grid, 256, 0, s>>>(a); break;
-    case M_SPLIT: metric_adjoint_kernel<M_SPLIT><<<grid, 256, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
+    for (int r0 = 0; r0 < a.n; r0 += MAX_GRID_Y) {
+        BwdMetricArgs b = a;
+        b.row0 = r0;
+        dim3 grid((a.kpad / 4 + 255) / 256, std::min(MAX_GRID_Y, a.n - r0));
+        switch (mode) {
+        case M_F64: metric_adjoint_kernel<M_F64><<<grid, 256, 0, s>>>(b); break;
+        case M_F32: metric_adjoint_kernel<M_F32><<<grid, 256, 0, s>>>(b); break;
+        case M_SPLIT: metric_adjoint_kernel<M_SPLIT><<<grid, 256, 0, s>>>(b); break;
+        default: return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t launch_normalise_adjoint(bool f64, const BwdNormArgs &a, hipStream_t s)
 {
-    dim3 grid((a.len + 255) / 256, a.n);
-    if (f64)
-        normalise_adjoint_kernel<double><<<grid, 256, 0, s>>>(a);
-    else
-        normalise_adjoint_kernel<float><<<grid, 256, 0, s>>>(a);
-    return hipGetLastError();
+    for (int r0 = 0; r0 < a.n; r0 += MAX_GRID_Y) {
+        BwdNormArgs b = a;
+        b.row0 = r0;
+        dim3 grid((a.len + 255) / 256, std::min(MAX_GRID_Y, a.n - r0));
+        if (f64)
+            normalise_adjoint_kernel<double><<<grid, 256, 0, s>>>(b);
+        else
+            normalise_adjoint_kernel<float><<<grid, 256, 0, s>>>(b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace plv

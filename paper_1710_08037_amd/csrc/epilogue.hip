@@ -49,8 +49,24 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
         const int64_t gi = (int64_t)I * BM + i, gj = (int64_t)J * BM + j;
         if (gi >= n || gj >= n || gi > gj)
             continue;
+        // slots added in index order; loads issued eight at a time so the
+        // sum is not a chain of dependent memory latencies
         double sr = 0.0, si = 0.0;
-        for (int c = 0; c < d.nslot; ++c) {
+        int c = 0;
+        for (; c + 8 <= d.nslot; c += 8) {
+            double vr[8], vi[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                vr[k] = part[(c + k) * cstride + e];
+                vi[k] = part[(c + k) * cstride + BM * BM + e];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                sr += vr[k];
+                si += vi[k];
+            }
+        }
+        for (; c < d.nslot; ++c) {
             sr += part[c * cstride + e];
             si += part[c * cstride + BM * BM + e];
         }

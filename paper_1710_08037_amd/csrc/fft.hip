@@ -14,13 +14,14 @@
 // with FFT_M(b) prepared once per length.  The inverse uses
 // IDFT(Y) = conj(DFT(conj(Y))) / t.
 //
-// Transforms: Stockham autosort passes of radix 16 (one smaller radix pass
-// when log2 M is not a multiple of 4), in natural order throughout.  Each
-// active thread holds PER = 16 elements in registers -- element
-// tid + e * (M / PER) of the sequence -- and does whole radix-R butterflies on
-// them; between passes the sequence goes through LDS (one hole every 16
-// elements against bank conflicts).  Twiddles come from a quarter-wave table
-// exp(-2 pi i m / M), m < M/4, in LDS, rotated by powers of -i.
+// Transforms: Stockham autosort passes of radix 8 (one smaller radix pass
+// when log2 M is not a multiple of 3), in natural order throughout.  Each
+// active thread holds PER = 8 elements (16 at M = 8192) in registers --
+// element tid + e * (M / PER) of the sequence -- and does whole radix-R
+// butterflies on them; between passes the sequence goes through LDS (one hole every 16
+// elements against bank conflicts).  Twiddles come from per-pass tables in
+// LDS, built once per work-group from the quarter-wave table
+// exp(-2 pi i m / M), m < M/4, by exact rotations.
 //
 // Bands: X stays in registers (and in LDS) after the forward transform.  A
 // band whose bin count K is small relative to the FFT cost is synthesised
@@ -86,8 +87,11 @@ __device__ inline void gst(cx<R> *p, int64_t i, cx<R> a)
 #ifndef PLV_FFT_LP
 #define PLV_FFT_LP 3
 #endif
-constexpr int LP = PLV_FFT_LP;  // log2 of the elements per thread (and of the main radix)
-__host__ __device__ constexpr int per_of(int logm) { return 1 << (logm < LP ? logm : LP); }
+constexpr int LP = PLV_FFT_LP;  // log2 of the main radix
+// Elements per thread: one radix-8 butterfly's worth, except at M = 8192
+// where 16 (two butterflies per pass) keep the work-group at 512 threads and
+// its registers within a 2-waves-per-SIMD budget (1024 threads would spill).
+__host__ __device__ constexpr int per_of(int logm) { return logm >= 13 ? 16 : 1 << (logm < LP ? logm : LP); }
 __host__ __device__ constexpr int nta_of(int logm) { return (1 << logm) / per_of(logm); }  // active threads
 __host__ __device__ constexpr int nt_of(int logm) { return nta_of(logm) < 64 ? 64 : nta_of(logm); }
 __host__ __device__ constexpr int lpad(int i) { return i + (i >> 4); }
@@ -95,6 +99,14 @@ __host__ __device__ constexpr int buf_elems(int logm) { return lpad((1 << logm) 
 __host__ __device__ constexpr int npass_of(int logm) { return logm <= LP ? 1 : logm / LP + (logm % LP ? 1 : 0); }
 // log2 of pass p's radix; the full-radix passes come first
 __host__ __device__ constexpr int lrad_of(int logm, int p) { return logm <= LP ? logm : (p < logm / LP ? LP : logm % LP); }
+// Per-pass twiddle tables: pass p >= 1 needs W^(r kk) for kk < NS = 2^(LP p)
+// and 1 <= r < radix, stored at ptab_off(p) + kk (radix - 1) + r - 1.
+__host__ __device__ constexpr int ptab_len(int logm, int p) { return (1 << (LP * p)) * ((1 << lrad_of(logm, p)) - 1); }
+__host__ __device__ constexpr int ptab_off(int logm, int p) { return p <= 1 ? 0 : ptab_off(logm, p - 1) + ptab_len(logm, p - 1); }
+__host__ __device__ constexpr int ptab_elems(int logm)
+{
+    return npass_of(logm) <= 1 ? 1 : ptab_off(logm, npass_of(logm) - 1) + ptab_len(logm, npass_of(logm) - 1);
+}
 
 // a * exp(-+2 pi i m / 16) (forward: minus), m a constant after unrolling.
 template <class R, bool INV>
@@ -192,18 +204,6 @@ __device__ inline cx<R> twiddle(const cx<R> *twq, int idx)
     return o;
 }
 
-// The twiddle table seen through an opaque zero offset, taken anew by each
-// transform: without it the compiler hoists every twiddle load of every
-// transform out of the row loop and keeps the values live across it, which
-// costs more registers than the reloads cost LDS bandwidth.
-template <class R>
-__device__ inline const cx<R> *opaque_table(const cx<R> *twq)
-{
-    int z;
-    asm volatile("v_mov_b32 %0, 0" : "=v"(z));
-    return twq + z;
-}
-
 // LDS index of element tid + e NTA (the natural register pattern); a base
 // plus constants when NTA is a multiple of 16.
 template <int LOGM>
@@ -221,7 +221,7 @@ __device__ inline int pat_addr(int tid, int e)
 // twiddled by W_(NS RR)^(r (j mod NS)) and transformed, and land at
 // (j - j mod NS) RR + j mod NS + r NS.
 template <class R, int LOGM, bool INV, int P>
-__device__ inline void fft_pass(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R> *twq, bool act)
+__device__ inline void fft_pass(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R> *ptab, bool act)
 {
     constexpr int PER = per_of(LOGM), NTA = nta_of(LOGM);
     constexpr int LR = lrad_of(LOGM, P), RR = 1 << LR, NS = 1 << (LP * P), BPT = PER / RR;
@@ -243,9 +243,12 @@ __device__ inline void fft_pass(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R
                 b[r] = v[q + r * BPT];
             if constexpr (NS > 1) {
                 const int kk = (tid + q * NTA) & (NS - 1);
+                const cx<R> *tw = ptab + ptab_off(LOGM, P) + kk * (RR - 1) - 1;
 #pragma unroll
-                for (int r = 1; r < RR; ++r)
-                    b[r] = cmul(b[r], twiddle<R, INV, LOGM>(twq, (r * kk) << (LOGM - LP * P - LR)));
+                for (int r = 1; r < RR; ++r) {
+                    const cx<R> w = tw[r];
+                    b[r] = cmul(b[r], INV ? cconj(w) : w);
+                }
             }
             dft<R, INV, RR>(b);
 #pragma unroll
@@ -270,16 +273,16 @@ __device__ inline void fft_pass(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R
         }
     }
     if constexpr (P + 1 < npass_of(LOGM))
-        fft_pass<R, LOGM, INV, P + 1>(v, buf, twq, act);
+        fft_pass<R, LOGM, INV, P + 1>(v, buf, ptab, act);
 }
 
 // Transform of the sequence held in v (natural pattern); the result is left
 // in buf in natural order (index lpad(k)), visible to the whole work-group.
 // Every thread of the work-group must call it.
 template <class R, int LOGM, bool INV>
-__device__ inline void fft_lds(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R> *twq, bool act)
+__device__ inline void fft_lds(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R> *ptab, bool act)
 {
-    fft_pass<R, LOGM, INV, 0>(v, buf, opaque_table(twq), act);
+    fft_pass<R, LOGM, INV, 0>(v, buf, ptab, act);
     __syncthreads();
 }
 
@@ -296,15 +299,27 @@ __global__ __launch_bounds__(256) void twiddle_kernel(cx<R> *tab, int logm)
     }
 }
 
+// Builds the per-pass twiddle tables of the work-group: the quarter-wave
+// table exp(-2 pi i m / M), m < M/4, is staged in `scratch` (the transform
+// buffer, free at this point) and each entry W^(r kk) of pass p is read off it
+// with an exact rotation by a power of -i.  Ends with a barrier.
 template <class R, int LOGM>
-__device__ inline void load_quarter(cx<R> *twq, const void *tw_tab)
+__device__ inline void build_tables(cx<R> *ptab, cx<R> *scratch, const void *tw_tab)
 {
-    constexpr int M = 1 << LOGM;
-    if constexpr (LOGM >= 2) {
-        const cx<R> *tg = (const cx<R> *)tw_tab;
+    constexpr int M = 1 << LOGM, NP = npass_of(LOGM);
+    if constexpr (NP > 1) {
         for (int k = threadIdx.x; k < M / 4; k += blockDim.x)
-            twq[k] = tg[k];
+            scratch[k] = gld((const cx<R> *)tw_tab, k);
+        __syncthreads();
+        for (int p = 1; p < NP; ++p) {
+            const int lr = lrad_of(LOGM, p), rr = 1 << lr, len = ptab_len(LOGM, p), off = ptab_off(LOGM, p);
+            for (int e = threadIdx.x; e < len; e += blockDim.x) {
+                const int kk = e / (rr - 1), r = e - kk * (rr - 1) + 1;
+                ptab[off + e] = twiddle<R, false, LOGM>(scratch, (r * kk) << (LOGM - LP * p - lr));
+            }
+        }
     }
+    __syncthreads();
 }
 
 // Per distinct row length t (one work-group per job): the root table
@@ -317,7 +332,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void chirp_kernel(const ChirpJob *jobs
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
     __shared__ cx<R> buf[buf_elems(LOGM)];
-    __shared__ cx<R> twq[M / 4 > 0 ? M / 4 : 1];
+    __shared__ cx<R> ptab[ptab_elems(LOGM)];
     const ChirpJob jb = jobs[blockIdx.x];
     const int t = jb.t, tid = threadIdx.x;
     cx<R> *roots = (cx<R> *)jb.roots;
@@ -328,7 +343,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void chirp_kernel(const ChirpJob *jobs
     }
     if (!jb.blue)
         return;
-    load_quarter<R, LOGM>(twq, jb.tw_tab);
+    build_tables<R, LOGM>(ptab, buf, jb.tw_tab);
     cx<R> *chirp = (cx<R> *)jb.chirp, *bh = (cx<R> *)jb.bhat;
     const bool act = tid < NTA;
     cx<R> v[PER];
@@ -347,8 +362,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void chirp_kernel(const ChirpJob *jobs
         }
         v[e] = c;
     }
-    __syncthreads();  // twq
-    fft_lds<R, LOGM, false>(v, buf, twq, act);
+    fft_lds<R, LOGM, false>(v, buf, ptab, act);
     for (int k = tid; k < M; k += blockDim.x)
         gst(bh, k, buf[lpad(k)]);
 }
@@ -475,11 +489,10 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
     __shared__ cx<R> buf[buf_elems(LOGM)];
-    __shared__ cx<R> twq[M / 4 > 0 ? M / 4 : 1];
+    __shared__ cx<R> ptab[ptab_elems(LOGM)];
     const int tid = threadIdx.x;
     const bool act = tid < NTA;
-    load_quarter<R, LOGM>(twq, a.hp[a.rows[0].prob].tw_tab);  // one table per launch (one M)
-    __syncthreads();
+    build_tables<R, LOGM>(ptab, buf, a.hp[a.rows[0].prob].tw_tab);  // one set per launch (one M)
 
     for (int ri = blockIdx.x; ri < a.nrows; ri += gridDim.x) {
         const RowRef rr = a.rows[ri];
@@ -497,7 +510,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
 #pragma unroll
             for (int e = 0; e < PER; ++e)
                 v[e] = cx<R>{x[tid0 + e * NTA], (R)0};
-            fft_lds<R, LOGM, false>(v, buf, twq, act);
+            fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
             for (int e = 0; e < PER; ++e)
                 X[e] = buf[pat_addr<LOGM>(tid0, e)];
@@ -508,11 +521,11 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
                 const cx<R> a = cscale(cconj(gld(ch, nc)), x[nc]);
                 v[e] = n < t ? a : cx<R>{0, 0};
             }
-            fft_lds<R, LOGM, false>(v, buf, twq, act);
+            fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
             for (int e = 0; e < PER; ++e)
                 v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
-            fft_lds<R, LOGM, true>(v, buf, twq, act);
+            fft_lds<R, LOGM, true>(v, buf, ptab, act);
             const R invm = (R)1 / (R)M;
 #pragma unroll
             for (int e = 0; e < PER; ++e) {
@@ -545,7 +558,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
                     v[e] = cscale(X[e], band_weight<R>(bb, tid0 + e * NTA, t));
-                fft_lds<R, LOGM, true>(v, buf, twq, act);
+                fft_lds<R, LOGM, true>(v, buf, ptab, act);
                 const R inv_t = (R)1 / (R)t;
                 store_band<R>(mode, g, hp, rr.row, [&](int n) { return cscale(buf[lpad(n)], inv_t); });
             } else {
@@ -556,11 +569,11 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
                     // X is 0 at n >= t, so the clamped chirp index changes nothing
                     v[e] = cconj(cmul(cscale(X[e], band_weight<R>(bb, n, t)), gld(ch, min(n, t - 1))));
                 }
-                fft_lds<R, LOGM, false>(v, buf, twq, act);
+                fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
                     v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
-                fft_lds<R, LOGM, true>(v, buf, twq, act);
+                fft_lds<R, LOGM, true>(v, buf, ptab, act);
                 const R zs = (R)1 / ((R)M * (R)t);
                 store_band<R>(mode, g, hp, rr.row,
                               [&](int n) { return cscale(cmul(gld(ch, n), cconj(buf[lpad(n)])), zs); });
@@ -579,11 +592,10 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
     __shared__ cx<R> buf[buf_elems(LOGM)];
-    __shared__ cx<R> twq[M / 4 > 0 ? M / 4 : 1];
+    __shared__ cx<R> ptab[ptab_elems(LOGM)];
     const int tid = threadIdx.x;
     const bool act = tid < NTA;
-    load_quarter<R, LOGM>(twq, a.hp[a.rows[0].prob].tw_tab);
-    __syncthreads();
+    build_tables<R, LOGM>(ptab, buf, a.hp[a.rows[0].prob].tw_tab);
 
     for (int ri = blockIdx.x; ri < a.nrows; ri += gridDim.x) {
         const RowRef rr = a.rows[ri];
@@ -609,7 +621,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
                     v[e] = v_at(tid0 + e * NTA);
-                fft_lds<R, LOGM, false>(v, buf, twq, act);
+                fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
                     S[e] = cadd(S[e], cscale(buf[pat_addr<LOGM>(tid0, e)], band_weight<R>(bb, tid0 + e * NTA, t)));
@@ -620,11 +632,11 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
                     const cx<R> a = cmul(v_at(n), cconj(gld(ch, min(n, t - 1))));  // v_at is 0 at n >= t
                     v[e] = a;
                 }
-                fft_lds<R, LOGM, false>(v, buf, twq, act);
+                fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
                     v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
-                fft_lds<R, LOGM, true>(v, buf, twq, act);
+                fft_lds<R, LOGM, true>(v, buf, ptab, act);
                 const R invm = (R)1 / (R)M;
 #pragma unroll
                 for (int e = 0; e < PER; ++e) {
@@ -640,7 +652,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
 #pragma unroll
             for (int e = 0; e < PER; ++e)
                 v[e] = S[e];
-            fft_lds<R, LOGM, true>(v, buf, twq, act);
+            fft_lds<R, LOGM, true>(v, buf, ptab, act);
             const R inv_t = (R)1 / (R)t;
             for (int n = tid; n < t; n += blockDim.x)
                 xb[n] = buf[lpad(n)].x * inv_t;
@@ -651,11 +663,11 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
                 const int n = tid0 + e * NTA;
                 v[e] = cconj(cmul(S[e], gld(ch, min(n, t - 1))));  // S is 0 at n >= t
             }
-            fft_lds<R, LOGM, false>(v, buf, twq, act);
+            fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
             for (int e = 0; e < PER; ++e)
                 v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
-            fft_lds<R, LOGM, true>(v, buf, twq, act);
+            fft_lds<R, LOGM, true>(v, buf, ptab, act);
             const R scale = (R)1 / ((R)M * (R)t);
             for (int n = tid; n < t; n += blockDim.x)
                 xb[n] = cmul(cconj(gld(ch, n)), buf[lpad(n)]).x * scale;

@@ -20,7 +20,7 @@ constexpr int VEC = 4;  // samples per thread
 template <int MODE>
 __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
 {
-    const int row = blockIdx.y;
+    const int row = a.row0 + blockIdx.y;
     const int s0 = (blockIdx.x * 256 + threadIdx.x) * VEC;
     if (s0 >= a.tpad)
         return;
@@ -46,16 +46,23 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
 
 hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s)
 {
-    dim3 grid((a.tpad + 256 * VEC - 1) / (256 * VEC), a.n);
-    switch (mode) {
-    case M_F64: normalise_kernel<M_F64><<<grid, 256, 0, s>>>(a); break;
-    case M_F32: normalise_kernel<M_F32><<<grid, 256, 0, s>>>(a); break;
-    case M_SPLIT: normalise_kernel<M_SPLIT><<<grid, 256, 0, s>>>(a); break;
-    case M_BF16: normalise_kernel<M_BF16><<<grid, 256, 0, s>>>(a); break;
-    case M_F16: normalise_kernel<M_F16><<<grid, 256, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
+    for (int r0 = 0; r0 < a.n; r0 += MAX_GRID_Y) {
+        NormArgs b = a;
+        b.row0 = r0;
+        dim3 grid((a.tpad + 256 * VEC - 1) / (256 * VEC), std::min(MAX_GRID_Y, a.n - r0));
+        switch (mode) {
+        case M_F64: normalise_kernel<M_F64><<<grid, 256, 0, s>>>(b); break;
+        case M_F32: normalise_kernel<M_F32><<<grid, 256, 0, s>>>(b); break;
+        case M_SPLIT: normalise_kernel<M_SPLIT><<<grid, 256, 0, s>>>(b); break;
+        case M_BF16: normalise_kernel<M_BF16><<<grid, 256, 0, s>>>(b); break;
+        case M_F16: normalise_kernel<M_F16><<<grid, 256, 0, s>>>(b); break;
+        default: return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 }  // namespace plv

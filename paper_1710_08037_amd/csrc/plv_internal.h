@@ -124,6 +124,7 @@ struct NormArgs {
     int64_t cstride;      // chunk-major layout of the planes (see above)
     int32_t chunk;
     int32_t tpad;
+    int32_t row0;         // first row of this launch (rows run on blockIdx.y)
 };
 
 // ------------------------------------------------- analytic signal (FFT) --
@@ -191,6 +192,7 @@ struct BwdMetricArgs {      // H = (Gbar + Gbar^H) / T: the product's A operand
     const void *g;           // forward complex G [n][n]
     const void *dplv, *diplv, *dciplv;  // upstream [n][n] (nullptr = 0)
     int32_t n, kpad;
+    int32_t row0;            // first row of this launch (rows run on blockIdx.y)
     double inv_t;
     uint8_t *h;              // planes [npad][kpad]
     int64_t plane_bytes;
@@ -204,9 +206,13 @@ struct BwdNormArgs {        // zbar = i Im(conj(u) ubar) u / |z|
     void *dst;               // output rows [n][ldd]; sample s of the window at q = s + off
     int64_t ldd;
     int32_t off, len, tw, n; // q runs over [0, len); outside the window -> 0
+    int32_t row0;            // first row of this launch (rows run on blockIdx.y)
 };
 
 // -------------------------------------------------------------- launchers --
+// Row-parallel launches put rows on gridDim.y, whose limit is 65535; the
+// launchers cover larger n in blocks of rows.
+constexpr int MAX_GRID_Y = 65535;
 // Each returns hipSuccess or the launch error.
 hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s);
 hipError_t launch_herk(int mode, const HerkArgs &a, int nwg, hipStream_t s);

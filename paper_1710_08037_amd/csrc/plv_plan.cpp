@@ -20,13 +20,13 @@ std::string msg(const char *fmt, long long a = 0, long long b = 0)
 // K-chunks of a problem computed alone.  Every (tile, chunk) item costs about
 // the same, so the launch takes ceil(items / slots) rounds of work-groups; the
 // chunk count is the one that fills those rounds best (fewest chunks among
-// equals), with no chunk longer than MAX_CHUNK and none shorter than MIN_CHUNK
+// equals), with no chunk longer than the mode's maximum and none shorter than MIN_CHUNK
 // unless T itself is.  Partial slots are capped by PARTIAL_BUDGET; beyond it
 // the chunks run in passes.
-void choose_chunks_single(GramPlan &g, int slots, int bm)
+void choose_chunks_single(GramPlan &g, int slots, int bm, int maxc)
 {
     const int kgr = g.tpad / PLV_KGRAN;
-    const int lo = std::max(1, (g.tpad + MAX_CHUNK - 1) / MAX_CHUNK);
+    const int lo = std::max(1, (g.tpad + maxc - 1) / maxc);
     const int hi = std::max(lo, std::min(kgr, std::max(1, g.tpad / MIN_CHUNK)));
     int best = lo;
     double best_eff = -1.0;
@@ -53,10 +53,10 @@ void choose_chunks_single(GramPlan &g, int slots, int bm)
 }
 
 // Inside a grouped launch every chunk of a problem has its own slot (one pass).
-void choose_chunks_grouped(GramPlan &g)
+void choose_chunks_grouped(GramPlan &g, int maxc)
 {
     const int kgr = g.tpad / PLV_KGRAN;
-    const int per = std::min(kgr, MAX_CHUNK / PLV_KGRAN);
+    const int per = std::min(kgr, maxc / PLV_KGRAN);
     g.chunk = per * PLV_KGRAN;
     g.nchunk = (kgr + per - 1) / per;
     g.nslot = g.nchunk;
@@ -257,7 +257,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         }
     } else if (grouped) {
         for (GramPlan &g : plan.grams) {
-            choose_chunks_grouped(g);
+            choose_chunks_grouped(g, max_chunk_of(mode));
             g.fused = g.nchunk == 1;
         }
         schedule_items(plan);
@@ -273,7 +273,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         plan.tile_off = off;
         off += align256(plan.ntiles * sizeof(TileRef));
     } else {
-        choose_chunks_single(plan.grams[0], slots, bm);
+        choose_chunks_single(plan.grams[0], slots, bm, max_chunk_of(mode));
         plan.grams[0].fused = plan.grams[0].nchunk == 1;
         plan.has_order = true;
         plan.order_off = off;

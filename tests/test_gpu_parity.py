@@ -214,3 +214,21 @@ def test_many_tiles_many_chunks_sampled_pairs(prec):
     ref = oracle.full_from_analytic(exact_input(z[rows], prec))
     sub = {k: v[np.ix_(rows, rows)] for k, v in got.items()}
     compare(sub, ref, TOL[prec], "N=2000 T=40000 %s" % prec)
+
+
+@pytest.mark.parametrize("prec", ["f32", "split_bf16"])
+@pytest.mark.parametrize("t", [16384, 60000])
+def test_coherent_signals_keep_fp32_accuracy(prec, t):
+    """The worst case of FP32 accumulation: pure tones of one frequency, so
+    every pair is perfectly locked (|G| = 1, G_ij = exp(i(a_i - a_j))) and the
+    rounding errors of the long sums do not cancel.  Every entry against the
+    oracle at the FP32 tolerance."""
+    n = 48
+    rng = np.random.default_rng(21)
+    a = rng.uniform(0, 2 * np.pi, size=n)
+    s = np.arange(t)
+    z = np.exp(1j * (0.0731 * s[None, :] + a[:, None])) * rng.uniform(0.5, 2.0, size=(n, 1))
+    z = z.astype(np.complex64)
+    got = gpu_full(z, prec)
+    ref = oracle.full_from_analytic(exact_input(z, prec))
+    compare(got, ref, TOL[prec], "coherent t=%d %s" % (t, prec))
