@@ -62,10 +62,8 @@ typedef enum {
 } plv_status;
 
 /* Arithmetic of the Gram contraction (the phasor planes and the MFMA inputs).
- * Accumulation is FP32 inside a K-chunk and FP64 across chunks for every mode
- * except PLV_PREC_F64, which is FP64 throughout.  K-chunks span at most 4096
- * samples in PLV_PREC_F32 and PLV_PREC_SPLIT_BF16 (so that coherent signals,
- * |G| near 1, keep FP32-level accuracy) and at most 16384 in the others. */
+ * Accumulation is FP32 inside a K-chunk of at most 16384 samples and FP64
+ * across chunks for every mode except PLV_PREC_F64, which is FP64 throughout. */
 typedef enum {
     PLV_PREC_F64 = 0,        /* FP64 input, FP64 phasors, FP64 MFMA; f64 / c128 outputs       */
     PLV_PREC_F32 = 1,        /* FP32 phasors, FP32 MFMA                                        */

@@ -257,7 +257,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         }
     } else if (grouped) {
         for (GramPlan &g : plan.grams) {
-            choose_chunks_grouped(g, max_chunk_of(mode));
+            choose_chunks_grouped(g, MAX_CHUNK);
             g.fused = g.nchunk == 1;
         }
         schedule_items(plan);
@@ -273,7 +273,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         plan.tile_off = off;
         off += align256(plan.ntiles * sizeof(TileRef));
     } else {
-        choose_chunks_single(plan.grams[0], slots, bm, max_chunk_of(mode));
+        choose_chunks_single(plan.grams[0], slots, bm, MAX_CHUNK);
         plan.grams[0].fused = plan.grams[0].nchunk == 1;
         plan.has_order = true;
         plan.order_off = off;

@@ -12,12 +12,6 @@
 namespace plv {
 
 constexpr int MAX_CHUNK = 16384;     // longest FP32 accumulation span of one work item (samples)
-// The modes that claim FP32-level accuracy (FP32, split-BF16) keep their FP32
-// accumulation spans shorter: for coherent signals (|G| near 1) the rounding
-// errors of a long FP32 accumulation do not cancel and grow with its length
-// (about 1e-5 at 16384 samples); at 4096 they stay below 3e-6.
-constexpr int MAX_CHUNK_FP32 = 4096;
-inline int max_chunk_of(int mode) { return (mode == M_F32 || mode == M_SPLIT) ? MAX_CHUNK_FP32 : MAX_CHUNK; }
 constexpr int MIN_CHUNK = 128;       // shortest K-chunk worth a work-group
 constexpr size_t PARTIAL_BUDGET = size_t(2) << 30;  // partial-slot bytes before T is split into passes
 
