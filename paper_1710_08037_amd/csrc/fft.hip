@@ -586,8 +586,9 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
 // dL/dx of one row: z_b = M_b x with M_b = IDFT diag(h_b) DFT Hermitian
 // (h_b real), so dL/dx = Re(sum_b M_b zbar_b) = Re(IDFT(sum_b h_b .*
 // DFT(zbar_b))), zbar_b being 0 outside the window.  The spectrum sum S stays
-// in registers (natural pattern).
-template <class R, int LOGM>
+// in registers (natural pattern); with a single band (ONE) it is the band's
+// own spectrum and needs no second register array.
+template <class R, int LOGM, bool ONE>
 __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArgs a)
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
@@ -604,11 +605,13 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
         const cx<R> *ch = (const cx<R> *)hp.chirp;
         const cx<R> *bh = (const cx<R> *)hp.bhat;
         const int tid0 = act ? tid : 0;
-        cx<R> v[PER], S[PER];
+        cx<R> v[PER], S[ONE ? 1 : PER];
+        if constexpr (!ONE) {
 #pragma unroll
-        for (int e = 0; e < PER; ++e)
-            S[e] = cx<R>{0, 0};
-        for (int b = 0; b < hp.nbands; ++b) {
+            for (int e = 0; e < PER; ++e)
+                S[e] = cx<R>{0, 0};
+        }
+        for (int b = 0; b < (ONE ? 1 : hp.nbands); ++b) {
             const BandBins bb = a.bins[hp.bin0 + b];
             const GramDesc g = a.gd[hp.gram0 + b];
             const cx<R> *zb = (const cx<R> *)g.zbuf + (int64_t)rr.row * g.ldz;
@@ -617,6 +620,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
                 const cx<R> z = gld(zb, min(max(s, 0), hp.tw - 1));
                 return (s >= 0 && s < hp.tw) ? z : cx<R>{0, 0};
             };
+            // v <- h_b .* DFT_t(zbar_b)
             if (!hp.blue) {
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
@@ -624,13 +628,12 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
                 fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
-                    S[e] = cadd(S[e], cscale(buf[pat_addr<LOGM>(tid0, e)], band_weight<R>(bb, tid0 + e * NTA, t)));
+                    v[e] = cscale(buf[pat_addr<LOGM>(tid0, e)], band_weight<R>(bb, tid0 + e * NTA, t));
             } else {
 #pragma unroll
                 for (int e = 0; e < PER; ++e) {
                     const int n = tid0 + e * NTA;
-                    const cx<R> a = cmul(v_at(n), cconj(gld(ch, min(n, t - 1))));  // v_at is 0 at n >= t
-                    v[e] = a;
+                    v[e] = cmul(v_at(n), cconj(gld(ch, min(n, t - 1))));  // v_at is 0 at n >= t
                 }
                 fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
@@ -642,16 +645,23 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
                 for (int e = 0; e < PER; ++e) {
                     const int k = tid0 + e * NTA;
                     const cx<R> d = cmul(cconj(gld(ch, min(k, t - 1))), buf[pat_addr<LOGM>(tid0, e)]);
-                    S[e] = cadd(S[e], cscale(d, k < t ? band_weight<R>(bb, k, t) * invm : (R)0));
+                    v[e] = cscale(d, k < t ? band_weight<R>(bb, k, t) * invm : (R)0);
                 }
             }
+            if constexpr (!ONE) {
+#pragma unroll
+                for (int e = 0; e < PER; ++e)
+                    S[e] = cadd(S[e], v[e]);
+            }
         }
-        // x_bar = Re(IDFT_t(S))
-        auto xb = gptr((R *)hp.xbar + (int64_t)rr.row * hp.ld);
-        if (!hp.blue) {
+        if constexpr (!ONE) {
 #pragma unroll
             for (int e = 0; e < PER; ++e)
                 v[e] = S[e];
+        }
+        // x_bar = Re(IDFT_t(S)), S in v
+        auto xb = gptr((R *)hp.xbar + (int64_t)rr.row * hp.ld);
+        if (!hp.blue) {
             fft_lds<R, LOGM, true>(v, buf, ptab, act);
             const R inv_t = (R)1 / (R)t;
             for (int n = tid; n < t; n += blockDim.x)
@@ -661,7 +671,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
 #pragma unroll
             for (int e = 0; e < PER; ++e) {
                 const int n = tid0 + e * NTA;
-                v[e] = cconj(cmul(S[e], gld(ch, min(n, t - 1))));  // S is 0 at n >= t
+                v[e] = cconj(cmul(v[e], gld(ch, min(n, t - 1))));  // S is 0 at n >= t
             }
             fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
@@ -696,8 +706,13 @@ hipError_t launch_sized(int kind, int mode, const HilbertArgs *ha, const ChirpJo
         const int nwg = grid_for(hilbert_kernel<R, LOGM>, NT, ha->nrows, cus);
         hilbert_kernel<R, LOGM><<<nwg, NT, 0, s>>>(*ha, mode);
     } else {
-        const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM>, NT, ha->nrows, cus);
-        hilbert_adjoint_kernel<R, LOGM><<<nwg, NT, 0, s>>>(*ha);
+        if (ha->nbands == 1) {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true>, NT, ha->nrows, cus);
+            hilbert_adjoint_kernel<R, LOGM, true><<<nwg, NT, 0, s>>>(*ha);
+        } else {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false>, NT, ha->nrows, cus);
+            hilbert_adjoint_kernel<R, LOGM, false><<<nwg, NT, 0, s>>>(*ha);
+        }
     }
     return hipGetLastError();
 }

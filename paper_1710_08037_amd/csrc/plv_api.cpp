@@ -461,6 +461,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             ha.nrows = class_count[c];
             ha.logm = plan.tw_logm[c];
             ha.gd = (const GramDesc *)(ws + plan.desc_off);
+            ha.nbands = nbands;
             if ((e = launch_hilbert(mode, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal kernel launch");
             tm.launched();
@@ -598,6 +599,7 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
     ha.hp = (const HilbertProb *)(ws + plan.hp_off);
     ha.bins = (const BandBins *)(ws + plan.bin_off);
     ha.gd = (const GramDesc *)(ws + plan.desc_off);
+    ha.nbands = nbands;
     if (real) {
         // analytic signal of the window, kept unnormalised in zbuf
         int nl = 0;

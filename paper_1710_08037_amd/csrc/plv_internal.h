@@ -50,7 +50,7 @@ enum Mode { M_F64 = 0, M_F32 = 1, M_SPLIT = 2, M_BF16 = 3, M_F16 = 4 };
 // cb bytes per complex element.
 __device__ inline uint8_t *plane_at(uint8_t *u, int64_t cstride, int chunk, int cb, int64_t row, int s)
 {
-    const int c = s / chunk;
+    const int c = s < chunk ? 0 : s / chunk;  // single-chunk problems skip the division
     return u + c * cstride + (row * chunk + (s - c * chunk)) * cb;
 }
 
@@ -166,6 +166,8 @@ struct HilbertArgs {
     int32_t nrows;
     int32_t logm;
     const GramDesc *gd;   // destinations of the phasor planes
+    int32_t nbands;       // bands per problem (the same for every problem of a call)
+    int32_t pad_;
 };
 
 // Set-up for one distinct row length t: its root table, and for a Bluestein
