@@ -72,6 +72,7 @@ def lib():
             L.oracle_phase.argtypes = [_D, _D, C.c_int64, _D]
             L.oracle_pair_means.argtypes = [_D, C.c_int64, C.c_int64, _I, _I, C.c_int64, _D, _D, C.c_int]
             L.oracle_metrics.argtypes = [_D, _D, C.c_int64, _D, _D, _D]
+            L.oracle_coherency.argtypes = [_D, _D, C.c_int64, C.c_int64, _I, _I, C.c_int64, _D, _D, C.c_int]
             L.oracle_metric_adjoint.argtypes = [_D, _D, _D, _D, _D, C.c_int64, _D, _D]
             L.oracle_phase_grad.argtypes = [_D, C.c_int64, C.c_int64, C.c_int64, _D, _D, _D, C.c_int64,
                                             C.c_int]
@@ -179,6 +180,48 @@ def pair_means(phi: np.ndarray, pairs: np.ndarray, nthreads: int | None = None) 
     lib().oracle_pair_means(_p(phi), t, t, pi.ctypes.data_as(_I), pj.ctypes.data_as(_I), len(pairs),
                             _p(gre), _p(gim), int(nthreads or threads()))
     return gre + 1j * gim
+
+
+def coherency(z: np.ndarray, pairs: np.ndarray, nthreads: int | None = None) -> np.ndarray:
+    """Complex coherency C_p = sum_t z_a conj(z_b) / sqrt(sum|z_a|^2 sum|z_b|^2)
+    for (a, b) = pairs[p] (Section II.B, Eq. 12; 0 where a row is all zero).
+    Coherence is |C|; imaginary and corrected imaginary coherency are
+    metrics(C)[1:] (the iPLV / ciPLV forms)."""
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    zr = np.ascontiguousarray(z.real)
+    zi = np.ascontiguousarray(z.imag)
+    pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    pi = np.ascontiguousarray(pairs[:, 0])
+    pj = np.ascontiguousarray(pairs[:, 1])
+    n, t = z.shape
+    assert pairs.size == 0 or (pairs.min() >= 0 and pairs.max() < n)
+    cre = np.empty(len(pairs))
+    cim = np.empty(len(pairs))
+    lib().oracle_coherency(_p(zr), _p(zi), t, t, pi.ctypes.data_as(_I), pj.ctypes.data_as(_I), len(pairs),
+                           _p(cre), _p(cim), int(nthreads or threads()))
+    return cre + 1j * cim
+
+
+def full_coherence(z: np.ndarray, nthreads=None) -> dict:
+    """Every pair of rows of z: {'coh', 'icoh', 'cicoh' [n, n] and 'c' [n, n]
+    complex coherency}, with coherence 1 and the others 0 on the diagonal."""
+    n = z.shape[0]
+    pr = upper_pairs(n)
+    c = coherency(z, pr, nthreads)
+    coh, icoh, cicoh = metrics(c)
+    out = {k: np.zeros((n, n)) for k in ("coh", "icoh", "cicoh")}
+    cc = np.zeros((n, n), dtype=np.complex128)
+    a, b = pr[:, 0], pr[:, 1]
+    for k, v in (("coh", coh), ("icoh", icoh), ("cicoh", cicoh)):
+        out[k][a, b] = v
+        out[k][b, a] = v
+    cc[a, b] = c
+    cc[b, a] = np.conj(c)
+    d = np.arange(n)
+    out["coh"][d, d] = 1.0
+    cc[d, d] = coherency(z, np.stack([d, d], 1), nthreads)
+    out["c"] = cc
+    return out
 
 
 def metrics(g: np.ndarray):

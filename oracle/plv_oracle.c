@@ -16,6 +16,9 @@
  *     pair-sample, i.e. the original per-pair formulation that the paper's
  *     matrix form (Eqs. 5-7) rewrites;
  *   - iPLV (Section II.C, Eq. 13) and ciPLV (Eq. 14) from the same mean;
+ *   - coherency (Section II.B, Eq. 12): amplitude-weighted cross sums over
+ *     the per-row powers; coherence is its magnitude, and the imaginary and
+ *     corrected imaginary coherency follow the iPLV / ciPLV forms;
  *   - the gradient of a loss on these metrics, derived in angle space
  *     (d mean / d phase), chained through atan2 and the linear analytic-signal
  *     map.  Not in the paper; it checks the library's adjoint.
@@ -288,6 +291,82 @@ void oracle_metrics(const double *gre, const double *gim, int64_t count, double 
         if (ciplv)
             ciplv[q] = d > 0.0 ? fabs(m) / sqrt(d) : 0.0;
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Coherency (Section II.B, Eq. 12)                                           */
+/* ------------------------------------------------------------------------- */
+
+/* Complex coherency of each listed pair of complex rows (Fourier coefficients
+ * over trials or windows, or analytic signals over time):
+ *   C[p] = sum_t X_a(t) conj(X_b(t)) / sqrt(sum_t |X_a(t)|^2 * sum_t |X_b(t)|^2)
+ * with (a, b) = (pi[p], pj[p]); its magnitude is the coherence of Eq. 12.  A
+ * pair with an all-zero row has no defined coherency and gets C = 0.  Sums in
+ * FP64 in sample order. */
+struct coh_job {
+    const double *zr, *zi;
+    int64_t ld, t;
+    const int64_t *pi, *pj;
+    double *cre, *cim;
+    int64_t p0, p1;
+};
+
+static double row_power(const double *zr, const double *zi, int64_t t)
+{
+    double s = 0.0;
+    for (int64_t k = 0; k < t; ++k)
+        s += zr[k] * zr[k] + zi[k] * zi[k];
+    return s;
+}
+
+static void *coh_worker(void *arg)
+{
+    struct coh_job *jb = (struct coh_job *)arg;
+    for (int64_t p = jb->p0; p < jb->p1; ++p) {
+        const double *ar = jb->zr + jb->pi[p] * jb->ld, *ai = jb->zi + jb->pi[p] * jb->ld;
+        const double *br = jb->zr + jb->pj[p] * jb->ld, *bi = jb->zi + jb->pj[p] * jb->ld;
+        double sr = 0.0, si = 0.0;
+        for (int64_t k = 0; k < jb->t; ++k) {
+            /* X_a conj(X_b) = (ar + i ai)(br - i bi) */
+            sr += ar[k] * br[k] + ai[k] * bi[k];
+            si += ai[k] * br[k] - ar[k] * bi[k];
+        }
+        const double pa = row_power(ar, ai, jb->t), pb = row_power(br, bi, jb->t);
+        const double den = sqrt(pa) * sqrt(pb);
+        jb->cre[p] = den > 0.0 ? sr / den : 0.0;
+        jb->cim[p] = den > 0.0 ? si / den : 0.0;
+    }
+    return NULL;
+}
+
+void oracle_coherency(const double *zr, const double *zi, int64_t ld, int64_t t, const int64_t *pi,
+                      const int64_t *pj, int64_t npairs, double *cre, double *cim, int nthreads)
+{
+    if (npairs <= 0)
+        return;
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > npairs)
+        nthreads = (int)npairs;
+    if (nthreads > 256)
+        nthreads = 256;
+    struct coh_job jobs[256];
+    pthread_t th[256];
+    for (int w = 0; w < nthreads; ++w) {
+        jobs[w].zr = zr;
+        jobs[w].zi = zi;
+        jobs[w].ld = ld;
+        jobs[w].t = t;
+        jobs[w].pi = pi;
+        jobs[w].pj = pj;
+        jobs[w].cre = cre;
+        jobs[w].cim = cim;
+        jobs[w].p0 = npairs * w / nthreads;
+        jobs[w].p1 = npairs * (w + 1) / nthreads;
+        pthread_create(&th[w], NULL, coh_worker, &jobs[w]);
+    }
+    for (int w = 0; w < nthreads; ++w)
+        pthread_join(th[w], NULL);
 }
 
 /* ------------------------------------------------------------------------- */
