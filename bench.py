@@ -20,7 +20,8 @@ end to end; ``batch`` 512 trials of uneven N in {68, 148, 360, 1000} and T in
 one grouped Gram launch; ``grad`` N = 2048 real f32 signals, T = 8192,
 forward plus adjoint of the ciPLV target loss; ``brain`` N = 15000 unit
 phasors, T = 1.2e6 (144 GB of complex64 made on the GPU), 200 planted lagged
-pairs, 16-bit MFMA with FP64 sums across K-chunks.
+pairs, 16-bit MFMA with FP64 sums across K-chunks; ``coherence`` coherency of
+N = 1024 complex coefficient rows x T = 60000.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -238,6 +239,28 @@ def bench_grad(args):
                     args, "bf16", {"n": n, "t": t, "prec": args.prec_batch}, {"stage_ms": stages})
 
 
+def bench_coherence(args):
+    """Coherency (Section II.B, Eq. 12) of N = 1024 complex rows x T = 60000
+    samples (amplitude-modulated coupled coefficients, complex64)."""
+    import numpy as np
+    import torch
+
+    import paper_1710_08037_amd as plv
+    import synth
+
+    n, t = N_SIG, T_SAMP
+    z = torch.from_numpy(synth.coefficients_mixed(n, t, seed=synth.seed_for(6, 1), dtype=np.complex64)).cuda()
+    prec = args.prec_batch
+    ms, stages = timed(lambda: plv.coherence(z, prec=prec), args.steps, args.warmup)
+    ps = n * (n - 1) // 2 * t
+    extra = {"stage_ms": stages}
+    if stages.get("gram"):
+        flops = FLOP_PER_PAIR_SAMPLE[prec] * ps
+        extra["gram_frac_of_peak"] = round(flops / (stages["gram"] / 1e3) / 1e12 / PEAK_TFLOPS[prec], 4)
+    return line_for("coherency: N=1024 complex coefficient rows x T=60000, amplitude-modulated mixtures",
+                    ps / (ms / 1e3), ms, args, "bf16", {"n": n, "t": t, "prec": prec}, extra)
+
+
 def bench_brain(args):
     """Whole-brain scale: N = 15000 unit phasors of T = 1.2e6 samples (144 GB
     of complex64, generated on the GPU), 200 planted constant-lag pairs;
@@ -339,7 +362,7 @@ def main():
                     help="paths to time (both: split-BF16 for `value`, FP32 beside it)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 3 times (counter calibration) and exit")
-    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain"])
+    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain", "coherence"])
     ap.add_argument("--prec-batch", default="split_bf16", help="precision of the batch and grad workloads")
     ap.add_argument("--prec-brain", default="bf16", choices=["bf16", "f16"], help="precision of the brain workload")
     args = ap.parse_args()
@@ -362,7 +385,8 @@ def main():
         print(json.dumps({"copy_ref_bytes": args.copy_ref}), flush=True)
         return
     if args.workload != "sensor":
-        fn = {"small": bench_small, "batch": bench_batch, "grad": bench_grad, "brain": bench_brain}[args.workload]
+        fn = {"small": bench_small, "batch": bench_batch, "grad": bench_grad, "brain": bench_brain,
+              "coherence": bench_coherence}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     z_np = synth.glag_analytic(N_SIG, T_SAMP, FS, 32, (8.0, 12.0), seed=synth.seed_for(2), dtype=np.complex64)

@@ -83,7 +83,8 @@ typedef enum {
     PLV_OP_FROM_ANALYTIC = 0,
     PLV_OP_FROM_REAL = 1,
     PLV_OP_BACKWARD_ANALYTIC = 2,
-    PLV_OP_BACKWARD_REAL = 3
+    PLV_OP_BACKWARD_REAL = 3,
+    PLV_OP_COHERENCE = 4
 } plv_op;
 
 typedef struct plv_ctx plv_ctx;
@@ -194,6 +195,24 @@ plv_status plv_from_analytic(plv_ctx *ctx, plv_prec prec, const plv_problem *pro
 plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
                          const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes,
                          void *stream);
+
+/* Coherency of complex rows (Section II.B, Eq. 12): Fourier coefficients of
+ * one frequency over trials or windows, or analytic signals over time, given
+ * exactly as for plv_from_analytic (interleaved c64; c128 for PLV_PREC_F64).
+ *   C_ij = sum_s z_i(s) conj(z_j(s)) / sqrt(sum_s |z_i|^2 * sum_s |z_j|^2)
+ * over the samples [t0, t1).  The problem's output fields are reused:
+ * `plv` <- coherence |C|, `iplv` <- imaginary coherency |Im C|, `ciplv` <-
+ * corrected imaginary coherency |Im C| / sqrt(1 - (Re C)^2) (radicand in FP64
+ * as (1 - Re)(1 + Re), 0 where it is <= 0), `g` <- the complex coherency C.
+ * The diagonal gets coherence 1, imaginary parts 0 and C_ii as computed; a
+ * row that is zero over the window gets C = 0 with every other row.  Each
+ * row is scaled by a power of two before the contraction (its largest
+ * component into [0.5, 1)), which C does not see, so the 16-bit modes stay in
+ * range.  Steps: row scale -> scaled planes -> Gram on MFMA -> fixed-order
+ * chunk sums and the diagonal powers -> normalised epilogue with mirrored
+ * store.  Outputs are [1][n][n]. */
+plv_status plv_coherence(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob, void *ws,
+                         size_t ws_bytes, void *stream);
 
 /* -------------------------------------------------------------- backward */
 

@@ -12,7 +12,7 @@ STATUS = {0: "PLV_OK", 1: "PLV_ERR_INVALID_ARG", 2: "PLV_ERR_WORKSPACE", 3: "PLV
           4: "PLV_ERR_UNSUPPORTED"}
 PREC = {"f64": 0, "f32": 1, "split_bf16": 2, "bf16": 3, "f16": 4}
 INPUT_ANALYTIC, INPUT_REAL = 0, 1
-OP_FROM_ANALYTIC, OP_FROM_REAL, OP_BACKWARD_ANALYTIC, OP_BACKWARD_REAL = 0, 1, 2, 3
+OP_FROM_ANALYTIC, OP_FROM_REAL, OP_BACKWARD_ANALYTIC, OP_BACKWARD_REAL, OP_COHERENCE = 0, 1, 2, 3, 4
 
 
 class Problem(C.Structure):
@@ -32,7 +32,7 @@ class Grad(C.Structure):
 # every symbol include/plv.h declares
 EXPORTS = ("plv_create", "plv_destroy", "plv_status_str", "plv_last_error", "plv_version",
            "plv_timing_enable", "plv_timing_read",
-           "plv_workspace_size", "plv_from_analytic", "plv_from_real", "plv_backward")
+           "plv_workspace_size", "plv_from_analytic", "plv_from_real", "plv_coherence", "plv_backward")
 
 STAGES = ("hilbert", "normalise", "gram", "epilogue", "backward")
 NSTAGES = 8
@@ -79,6 +79,8 @@ def lib():
             L.plv_workspace_size.restype = C.c_int
             L.plv_from_analytic.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64, P, C.c_size_t, P]
             L.plv_from_analytic.restype = C.c_int
+            L.plv_coherence.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64, P, C.c_size_t, P]
+            L.plv_coherence.restype = C.c_int
             L.plv_from_real.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64, C.POINTER(Band), C.c_int32,
                                         C.c_double, P, C.c_size_t, P]
             L.plv_from_real.restype = C.c_int

@@ -123,6 +123,40 @@ def from_analytic(z, prec="split_bf16", window=None, want=ALL, want_g=False):
     return from_analytic_batch([z], prec, None if window is None else [window], want, want_g)[0]
 
 
+def coherence_batch(zs, prec="split_bf16", windows=None, want=ALL, want_g=False):
+    """Coherency (Section II.B, Eq. 12) of several problems of complex rows in
+    one call: Fourier coefficients over trials or windows, or analytic signals.
+
+    zs: list of complex GPU tensors [n_k, t_k] (complex64; complex128 for f64).
+    Returns a list of dicts of [n_k, n_k] tensors: 'coh' (coherence |C|),
+    'icoh' (|Im C|), 'cicoh' (|Im C| / sqrt(1 - Re C^2)) and 'c' (complex C).
+    `want` names the real outputs by their PLV-field names (plv, iplv, ciplv).
+    """
+    p = _prec_id(prec)
+    dev = zs[0].device
+    cd = torch.complex128 if p == 0 else torch.complex64
+    rd = torch.float64 if p == 0 else torch.float32
+    outs, probs = [], []
+    for k, z in enumerate(zs):
+        if z.dtype != cd:
+            raise TypeError("prec %s needs %s input, got %s" % (prec, cd, z.dtype))
+        o = _outputs(z.shape[0], 1, rd, cd, dev, want, want_g)
+        outs.append(o)
+        probs.append(_problem(z, None if windows is None else windows[k], o))
+    arr = _abi.problems(probs)
+    ctx = context(dev)
+    ws = _workspace(ctx, _abi.OP_COHERENCE, p, arr, None, 1, dev)
+    _abi.check(_abi.lib().plv_coherence(ctx.handle, p, arr, len(probs), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                        _stream(dev)), ctx.handle)
+    names = {"plv": "coh", "iplv": "icoh", "ciplv": "cicoh", "g": "c"}
+    return [{names[k]: (v[0] if v is not None else None) for k, v in o.items()} for o in outs]
+
+
+def coherence(z, prec="split_bf16", window=None, want=ALL, want_g=False):
+    """Coherency of one problem of complex rows z [n, t]; see coherence_batch."""
+    return coherence_batch([z], prec, None if window is None else [window], want, want_g)[0]
+
+
 def from_real_batch(xs, fs, bands=None, prec="split_bf16", windows=None, want=ALL, want_g=False):
     """PLV/iPLV/ciPLV of real signals, the analytic signal formed on the GPU.
 

@@ -70,11 +70,52 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
             sr += part[c * cstride + e];
             si += part[c * cstride + BM * BM + e];
         }
-        store_entry<MODE>(d, gi, gj, sr * inv_t, si * inv_t);
+        if (args.coherence) {
+            // C = S_ij / sqrt(S_ii S_jj) with the same fixed-order sums on the
+            // diagonal (so C_ii = 1 exactly); 0 where a row is all zero
+            const double den = sqrt(d.diag[gi]) * sqrt(d.diag[gj]);
+            store_entry<MODE>(d, gi, gj, den > 0.0 ? sr / den : 0.0, den > 0.0 ? si / den : 0.0);
+        } else {
+            store_entry<MODE>(d, gi, gj, sr * inv_t, si * inv_t);
+        }
     }
 }
 
+// d[i] = sum over slots (in index order) of Re G(i, i), read from the
+// partials of diagonal tile (I, I), I = i / BM: the same sums the epilogue
+// forms for the diagonal entry.
+template <int MODE>
+__global__ __launch_bounds__(256) void diag_kernel(GramDesc d)
+{
+    constexpr int BM = tile_of(MODE);
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= d.n)
+        return;
+    const int I = i / BM, r = i - I * BM;
+    const int tile = I * d.ntile - I * (I - 1) / 2;  // row-major upper index of (I, I)
+    auto part = gptr((const double *)d.partial + (int64_t)tile * 2 * BM * BM + (int64_t)r * BM + r);
+    const int64_t cstride = (int64_t)d.nupper * 2 * BM * BM;
+    double s = 0.0;
+    for (int c = 0; c < d.nslot; ++c)
+        s += part[c * cstride];
+    gptr(d.diag)[i] = s;
+}
+
 }  // namespace
+
+hipError_t launch_diag(int mode, const GramDesc &g, hipStream_t s)
+{
+    const int grid = (g.n + 255) / 256;
+    switch (mode) {
+    case M_F64: diag_kernel<M_F64><<<grid, 256, 0, s>>>(g); break;
+    case M_F32: diag_kernel<M_F32><<<grid, 256, 0, s>>>(g); break;
+    case M_SPLIT: diag_kernel<M_SPLIT><<<grid, 256, 0, s>>>(g); break;
+    case M_BF16: diag_kernel<M_BF16><<<grid, 256, 0, s>>>(g); break;
+    case M_F16: diag_kernel<M_F16><<<grid, 256, 0, s>>>(g); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, hipStream_t s)
 {

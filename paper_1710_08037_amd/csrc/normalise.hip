@@ -1,4 +1,5 @@
-// normalise.hip -- analytic signal -> unit phasors (Section II.A, Eq. 4).
+// normalise.hip -- analytic signal -> unit phasors (Section II.A, Eq. 4), and
+// for coherency (Section II.B, Eq. 12) the rows scaled by a power of two.
 //
 // u = z / |z| replaces the angle() + exp() of the per-pair formulation.  |z| is
 // formed from components rescaled by an exact power of two, so FP32 neither
@@ -29,6 +30,7 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
     typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
     auto src = gptr((const cplx_t *)a.in + (int64_t)row * a.ld + a.t0);
     real_t ur[VEC], ui[VEC];
+    const real_t sc = a.scale ? (real_t)a.scale[row] : (real_t)1;  // a power of two: exact
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         const int s = s0 + v;
@@ -36,13 +38,62 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
         ui[v] = 0;
         if (s < a.tw) {
             cplx_t z = src[s];
-            unit_phasor(z.x, z.y, ur[v], ui[v]);
+            if (a.scale) {
+                ur[v] = z.x * sc;
+                ui[v] = z.y * sc;
+            } else {
+                unit_phasor(z.x, z.y, ur[v], ui[v]);
+            }
         }
     }
     store4<MODE>(dst, a.plane_bytes, ur, ui);
 }
 
+// One work-group per row: the largest |Re z| or |Im z| over the window, and
+// its exponent e (frexp convention, m = f 2^e with f in [0.5, 1)), give the
+// scale 2^-e.  A zero row gets 1.  The exponent is clamped to [-126, 126] so
+// the scale is a normal FP32 number too.
+template <class R>
+__global__ __launch_bounds__(256) void row_scale_kernel(ScaleArgs a)
+{
+    typedef typename std::conditional<sizeof(R) == 8, vd2, vf2>::type cplx_t;
+    __shared__ R part[256];
+    const int row = blockIdx.x;
+    auto src = gptr((const cplx_t *)a.in + (int64_t)row * a.ld + a.t0);
+    R m = 0;
+    for (int s = threadIdx.x; s < a.tw; s += 256) {
+        const cplx_t z = src[s];
+        m = fmax(m, fmax(fabs(z.x), fabs(z.y)));
+    }
+    part[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const R mx = part[0];
+        int e = 0;
+        if (mx > 0)
+            (void)frexp(mx, &e);
+        e = e < -126 ? -126 : (e > 126 ? 126 : e);
+        a.scale[row] = ldexp(1.0, -e);
+    }
+}
+
 }  // namespace
+
+hipError_t launch_row_scale(bool f64, const ScaleArgs &a, hipStream_t s)
+{
+    if (a.n <= 0)
+        return hipSuccess;
+    if (f64)
+        row_scale_kernel<double><<<a.n, 256, 0, s>>>(a);
+    else
+        row_scale_kernel<float><<<a.n, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
 
 hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s)
 {

@@ -468,9 +468,23 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
         }
     } else {
         StageTimer tm(ctx, PLV_STAGE_NORMALISE, s);
+        const bool coh = plan.op == PLV_OP_COHERENCE;
         for (const GramPlan &gp : plan.grams) {
             const plv_problem &p = probs[gp.prob];
+            if (coh) {
+                ScaleArgs sa{};
+                sa.in = p.in;
+                sa.ld = p.ld;
+                sa.t0 = gp.t0;
+                sa.tw = gp.t;
+                sa.n = gp.n;
+                sa.scale = (double *)(ws + gp.scale_off);
+                if ((e = launch_row_scale(mode == M_F64, sa, s)) != hipSuccess)
+                    return hip_fail(ctx, e, "row scale kernel launch");
+                tm.launched();
+            }
             NormArgs na{};
+            na.scale = coh ? (const double *)(ws + gp.scale_off) : nullptr;
             na.in = p.in;
             na.ld = p.ld;
             na.t0 = gp.t0;
@@ -508,6 +522,12 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
         StageTimer tm(ctx, PLV_STAGE_EPILOGUE, s);
         EpiArgs ea{};
         ea.g = d;
+        if (plan.op == PLV_OP_COHERENCE) {
+            if ((e = launch_diag(mode, d, s)) != hipSuccess)
+                return hip_fail(ctx, e, "diagonal kernel launch");
+            tm.launched();
+            ea.coherence = true;
+        }
         if ((e = launch_epilogue(mode, ea, d.nupper, s)) != hipSuccess)
             return hip_fail(ctx, e, "epilogue kernel launch");
         tm.launched();
@@ -528,6 +548,13 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
     StageTimer tm(ctx, PLV_STAGE_EPILOGUE, s);
     EpiArgs ea{};
     ea.gd = ha.gd;
+    if (plan.op == PLV_OP_COHERENCE) {
+        for (const GramDesc &d : gd)
+            if ((e = launch_diag(mode, d, s)) != hipSuccess)
+                return hip_fail(ctx, e, "diagonal kernel launch");
+        tm.launched((int)gd.size());
+        ea.coherence = true;
+    }
     ea.tiles = (const TileRef *)(ws + plan.tile_off);
     if ((e = launch_epilogue(mode, ea, (int)tiles.size(), s)) != hipSuccess)
         return hip_fail(ctx, e, "epilogue kernel launch");
@@ -540,6 +567,16 @@ plv_status plv_from_analytic(plv_ctx *ctx, plv_prec prec, const plv_problem *pro
 {
     Plan plan;
     plv_status st = begin(ctx, PLV_OP_FROM_ANALYTIC, prec, probs, nprob, nullptr, 1, ws, ws_bytes, plan);
+    if (st != PLV_OK)
+        return st;
+    return enqueue_forward(ctx, plan, probs, nullptr, 1, 0.0, (uint8_t *)ws, (hipStream_t)stream);
+}
+
+plv_status plv_coherence(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob, void *ws,
+                         size_t ws_bytes, void *stream)
+{
+    Plan plan;
+    plv_status st = begin(ctx, PLV_OP_COHERENCE, prec, probs, nprob, nullptr, 1, ws, ws_bytes, plan);
     if (st != PLV_OK)
         return st;
     return enqueue_forward(ctx, plan, probs, nullptr, 1, 0.0, (uint8_t *)ws, (hipStream_t)stream);

@@ -85,6 +85,7 @@ struct GramDesc {
     int64_t ldc;
     void *zbuf;           // FFT stage of the backward: complex z of the window
     int64_t ldz;          //   [n][ldz] written instead of phasor planes
+    double *diag;         // coherency: [npad] row powers sum |z_i|^2 from the Gram's diagonal
 };
 
 // One unit of Gram work: a (problem, tile, chunk) triple.
@@ -110,6 +111,7 @@ struct EpiArgs {
     GramDesc g;             // the single problem when tiles == nullptr
     const GramDesc *gd;
     const TileRef *tiles;   // grouped launch, or nullptr
+    bool coherence;         // divide by sqrt(d_i d_j) (GramDesc::diag) instead of T
 };
 
 // Normalisation job: rows of one problem -> planes of one Gram problem.
@@ -125,6 +127,16 @@ struct NormArgs {
     int32_t chunk;
     int32_t tpad;
     int32_t row0;         // first row of this launch (rows run on blockIdx.y)
+    const double *scale;  // coherency: per-row power-of-two scale (no unit normalisation), else nullptr
+};
+
+// Coherency: per-row scale 2^-e with e the exponent of the row's largest
+// component over the window, so scaled rows peak in [0.5, 1).
+struct ScaleArgs {
+    const void *in;       // complex rows (c64 or c128)
+    int64_t ld, t0;
+    int32_t tw, n;
+    double *scale;        // [n]
 };
 
 // ------------------------------------------------- analytic signal (FFT) --
@@ -219,6 +231,9 @@ constexpr int MAX_GRID_Y = 65535;
 hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s);
 hipError_t launch_herk(int mode, const HerkArgs &a, int nwg, hipStream_t s);
 hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, hipStream_t s);
+hipError_t launch_row_scale(bool f64, const ScaleArgs &a, hipStream_t s);
+// d[i] = fixed-order sum over slots of the diagonal entries of G's partials
+hipError_t launch_diag(int mode, const GramDesc &g, hipStream_t s);
 // Occupancy (work-groups per CU) of the Gram kernel of `mode`.
 int herk_occupancy(int mode);
 // FFT stage (fft.hip).  f64 selects double precision tables and transforms.

@@ -126,7 +126,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         why = "unknown precision";
         return PLV_ERR_INVALID_ARG;
     }
-    if ((int)op < 0 || (int)op > 3) {
+    if ((int)op < 0 || (int)op > 4) {
         why = "unknown op";
         return PLV_ERR_INVALID_ARG;
     }
@@ -258,7 +258,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
     } else if (grouped) {
         for (GramPlan &g : plan.grams) {
             choose_chunks_grouped(g, MAX_CHUNK);
-            g.fused = g.nchunk == 1;
+            g.fused = g.nchunk == 1 && op != PLV_OP_COHERENCE;  // coherency needs every diagonal first
         }
         schedule_items(plan);
         for (const GramPlan &g : plan.grams)
@@ -274,7 +274,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         off += align256(plan.ntiles * sizeof(TileRef));
     } else {
         choose_chunks_single(plan.grams[0], slots, bm, MAX_CHUNK);
-        plan.grams[0].fused = plan.grams[0].nchunk == 1;
+        plan.grams[0].fused = plan.grams[0].nchunk == 1 && op != PLV_OP_COHERENCE;
         plan.has_order = true;
         plan.order_off = off;
         off += align256((size_t)plan.grams[0].nupper * sizeof(int32_t));
@@ -376,6 +376,14 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         g.part_off = off;
         off += align256((size_t)g.nslot * g.nupper * 2 * bm * bm * sizeof(double));
     }
+    if (op == PLV_OP_COHERENCE) {
+        for (GramPlan &g : plan.grams) {
+            g.scale_off = off;
+            off += align256((size_t)g.n * sizeof(double));
+            g.diag_off = off;
+            off += align256((size_t)g.npad * sizeof(double));
+        }
+    }
     plan.total = off;
     return PLV_OK;
 }
@@ -400,6 +408,7 @@ void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd)
         d.nslot = g.nslot;
         d.fused = g.fused ? 1 : 0;
         d.partial = g.fused ? nullptr : (double *)(ws + g.part_off);
+        d.diag = plan.op == PLV_OP_COHERENCE ? (double *)(ws + g.diag_off) : nullptr;
         d.plv = g.plv;
         d.iplv = g.iplv;
         d.ciplv = g.ciplv;

@@ -30,6 +30,7 @@ struct GramPlan {
     size_t w_off = 0;                  // W = conj(U^T) planes (B operand)
     size_t c_off = 0;                  // ubar [n][t] complex
     size_t z_off = 0;                  // real input: z, then zbar, [n][t] complex
+    size_t scale_off = 0, diag_off = 0; // coherency: row scales [n], row powers [npad] (FP64)
     void *plv = nullptr, *iplv = nullptr, *ciplv = nullptr, *g = nullptr;
 };
 

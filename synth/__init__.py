@@ -15,6 +15,8 @@ Generators
                    constant-lag pairs with Gaussian jitter.
 ``batch_shapes``   (N, T) per trial for the uneven grouped workload.
 ``sparse_target``  the seeded sparse ciPLV target C* of the differentiable case.
+``coefficients_mixed`` complex coefficients with amplitude modulation and
+                   lagged mixtures of shared sources (coherency inputs).
 
 The paper's recordings (MEG source space, 1 kHz, 4 s trials, alpha band,
 Section III.A) are not available; these stand in for them with the same shapes.
@@ -167,3 +169,21 @@ def sparse_target(n: int, seed: int, frac: float = 0.01, lo: float = 0.2, hi: fl
     c[iu[pick], ju[pick]] = vals
     c[ju[pick], iu[pick]] = vals
     return c
+
+
+def coefficients_mixed(n: int, t: int, seed: int, k: int = 4, noise: float = 0.5,
+                       dtype=np.complex128) -> np.ndarray:
+    """Complex rows [n, t] standing in for Fourier coefficients over trials:
+    K latent complex Gaussian sources whose amplitude is modulated per sample
+    (log-normal, sigma 0.7, so samples carry very different weights), mixed
+    into each row with Dirichlet(0.5) weights and uniform lags in [0, pi),
+    plus complex white noise of variance `noise` per component."""
+    rng = np.random.default_rng(seed)
+    src = (rng.standard_normal((k, t)) + 1j * rng.standard_normal((k, t))) / math.sqrt(2.0)
+    src *= np.exp(0.7 * rng.standard_normal((1, t)))
+    w = rng.dirichlet(0.5 * np.ones(k), size=n)
+    lag = rng.uniform(0.0, math.pi, size=(n, k))
+    x = (w * np.exp(1j * lag)) @ src
+    x += math.sqrt(noise) * (rng.standard_normal((n, t)) + 1j * rng.standard_normal((n, t)))
+    return x.astype(dtype, copy=False)
+
