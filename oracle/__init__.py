@@ -21,6 +21,10 @@ What is computed, and where it comes from in the paper (Bruna, Maestu, Pereda,
                     return them.
 * ``grad_*``        gradient of a loss on the metrics, in angle space (not in
                     the paper; it checks the library's adjoint).
+* ``coherency``     Section II.B, Eq. 12: amplitude-weighted cross sums over the
+                    rows' powers (coherence = |C|); ``full_coherence``.
+* ``full_over_trials`` Eq. 1 (matrix form Eq. 8): Lachaux's PLV(t), the mean
+                    over trials at each time point.
 
 Readings of the paper that the oracle takes (orientation of G, absolute
 iPLV/ciPLV, the 1/T normaliser, the z = 0 rule, the ciPLV radicand) are listed
@@ -261,6 +265,20 @@ def full_from_phase(phi: np.ndarray, nthreads=None) -> dict:
         M[a, b] = v
         M[b, a] = v
     return {"g": G, "plv": P, "iplv": I, "ciplv": Cc}
+
+
+def full_over_trials(z: np.ndarray, window=None, nthreads=None) -> dict:
+    """Lachaux's time-resolved PLV across trials (Eq. 1): z is [ntr, N, T]
+    analytic signals; for each time point t in the window, every pair's mean
+    over the trials n of exp(i(phi_i(t, n) - phi_j(t, n))), assembled like
+    full_from_phase.  Returns [T', N, N] arrays."""
+    z = np.asarray(z)
+    t0, t1 = (0, z.shape[2]) if window is None else window
+    outs = []
+    for t in range(t0, t1):
+        phi = phase(np.ascontiguousarray(z[:, :, t].T))   # [N, ntr]: trials are the samples
+        outs.append(full_from_phase(phi, nthreads))
+    return {k: np.stack([o[k] for o in outs]) for k in outs[0]}
 
 
 def full_from_analytic(z: np.ndarray, window=None, nthreads=None) -> dict:
