@@ -21,7 +21,8 @@ one grouped Gram launch; ``grad`` N = 2048 real f32 signals, T = 8192,
 forward plus adjoint of the ciPLV target loss; ``brain`` N = 15000 unit
 phasors, T = 1.2e6 (144 GB of complex64 made on the GPU), 200 planted lagged
 pairs, 16-bit MFMA with FP64 sums across K-chunks; ``coherence`` coherency of
-N = 1024 complex coefficient rows x T = 60000.
+N = 1024 complex coefficient rows x T = 60000; ``trials`` PLV across 40 trials
+for 148 signals at each of 4000 time points.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -261,6 +262,27 @@ def bench_coherence(args):
                     ps / (ms / 1e3), ms, args, "bf16", {"n": n, "t": t, "prec": prec}, extra)
 
 
+def bench_trials(args):
+    """Lachaux's PLV across trials (Eq. 1): 148 signals x 40 trials x 4000 time
+    points (4 s at 1 kHz), complex64 trial-major; one PLV matrix per time point."""
+    import numpy as np
+    import torch
+
+    import paper_1710_08037_amd as plv
+    import synth
+
+    n, ntr, t = 148, 40, 4000
+    seed = synth.seed_for(7, 100)
+    z = torch.from_numpy(np.stack([synth.glag_analytic(n, t, 1000.0, 8, (8.0, 12.0), seed=seed + k,
+                                                       dtype=np.complex64) for k in range(ntr)])).cuda()
+    prec = args.prec_batch
+    ms, stages = timed(lambda: plv.over_trials(z, prec=prec), args.steps, args.warmup)
+    ps = n * (n - 1) // 2 * ntr * t
+    return line_for("PLV across trials: 148 signals x 40 trials x 4000 time points, complex64",
+                    ps / (ms / 1e3), ms, args, "bf16", {"n": n, "trials": ntr, "t": t, "prec": prec},
+                    {"stage_ms": stages, "matrices_per_s": round(t / (ms / 1e3), 1)})
+
+
 def bench_brain(args):
     """Whole-brain scale: N = 15000 unit phasors of T = 1.2e6 samples (144 GB
     of complex64, generated on the GPU), 200 planted constant-lag pairs;
@@ -362,7 +384,7 @@ def main():
                     help="paths to time (both: split-BF16 for `value`, FP32 beside it)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 3 times (counter calibration) and exit")
-    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain", "coherence"])
+    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain", "coherence", "trials"])
     ap.add_argument("--prec-batch", default="split_bf16", help="precision of the batch and grad workloads")
     ap.add_argument("--prec-brain", default="bf16", choices=["bf16", "f16"], help="precision of the brain workload")
     args = ap.parse_args()
@@ -386,7 +408,7 @@ def main():
         return
     if args.workload != "sensor":
         fn = {"small": bench_small, "batch": bench_batch, "grad": bench_grad, "brain": bench_brain,
-              "coherence": bench_coherence}[args.workload]
+              "coherence": bench_coherence, "trials": bench_trials}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     z_np = synth.glag_analytic(N_SIG, T_SAMP, FS, 32, (8.0, 12.0), seed=synth.seed_for(2), dtype=np.complex64)

@@ -214,6 +214,35 @@ plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, 
 plv_status plv_coherence(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob, void *ws,
                          size_t ws_bytes, void *stream);
 
+/* Lachaux's time-resolved PLV across trials (Eq. 1; matrix form Eq. 8): for
+ * every time point t of [t0, t1), the measures of the n signals with the
+ * trials as the contracted axis,
+ *   G_ij(t) = (1/ntr) sum_k u_i(t, k) conj(u_j(t, k)),  u = z / |z| (Eq. 4),
+ * PLV(t) = |G(t)|, iPLV(t) = |Im G(t)|, ciPLV(t) as in plv_from_analytic.
+ * Sample (trial k, signal i, time t) of the analytic signals is at
+ * in + k*tstride + i*ld + t*sstride complex elements (c64; c128 for
+ * PLV_PREC_F64), so trial-major [ntr][n][T] data (tstride = n*ld, sstride = 1)
+ * and the signals x samples x trials layout (tstride = 1, sstride = ntr,
+ * ld = T*ntr) are both accepted; reads coalesce best with sstride = 1.
+ * Outputs are [t1 - t0][n][n] (g complex), NULL to skip.  Every time point
+ * is one Gram problem of n rows and ntr samples; all of them run in one
+ * grouped launch. */
+typedef struct {
+    int64_t n;        /* signals, >= 1                                          */
+    int64_t ntr;      /* trials (the contracted axis), 1 <= ntr <= 2^17          */
+    int64_t t;        /* time samples per signal and trial, >= 1                */
+    int64_t ld;       /* stride between signals, complex elements, >= 1          */
+    int64_t tstride;  /* stride between trials, complex elements, >= 1           */
+    int64_t sstride;  /* stride between time samples, complex elements, >= 1     */
+    int64_t t0, t1;   /* time points [t0, t1) get a matrix each; t1 = 0 means t */
+    const void *in;
+    void *plv, *iplv, *ciplv, *g;
+} plv_trials;
+
+plv_status plv_trials_workspace_size(const plv_ctx *ctx, plv_prec prec, const plv_trials *p, size_t *bytes);
+plv_status plv_over_trials(plv_ctx *ctx, plv_prec prec, const plv_trials *p, void *ws, size_t ws_bytes,
+                           void *stream);
+
 /* -------------------------------------------------------------- backward */
 
 /* Gradient of a scalar loss with respect to the input, given dL/d(outputs).

@@ -21,6 +21,13 @@ class Problem(C.Structure):
                 ("g", C.c_void_p)]
 
 
+class Trials(C.Structure):
+    _fields_ = [("n", C.c_int64), ("ntr", C.c_int64), ("t", C.c_int64), ("ld", C.c_int64),
+                ("tstride", C.c_int64), ("sstride", C.c_int64), ("t0", C.c_int64), ("t1", C.c_int64),
+                ("in_", C.c_void_p), ("plv", C.c_void_p), ("iplv", C.c_void_p), ("ciplv", C.c_void_p),
+                ("g", C.c_void_p)]
+
+
 class Band(C.Structure):
     _fields_ = [("f_lo", C.c_double), ("f_hi", C.c_double)]
 
@@ -32,7 +39,8 @@ class Grad(C.Structure):
 # every symbol include/plv.h declares
 EXPORTS = ("plv_create", "plv_destroy", "plv_status_str", "plv_last_error", "plv_version",
            "plv_timing_enable", "plv_timing_read",
-           "plv_workspace_size", "plv_from_analytic", "plv_from_real", "plv_coherence", "plv_backward")
+           "plv_workspace_size", "plv_from_analytic", "plv_from_real", "plv_coherence",
+           "plv_trials_workspace_size", "plv_over_trials", "plv_backward")
 
 STAGES = ("hilbert", "normalise", "gram", "epilogue", "backward")
 NSTAGES = 8
@@ -81,6 +89,10 @@ def lib():
             L.plv_from_analytic.restype = C.c_int
             L.plv_coherence.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64, P, C.c_size_t, P]
             L.plv_coherence.restype = C.c_int
+            L.plv_trials_workspace_size.argtypes = [P, C.c_int, C.POINTER(Trials), C.POINTER(C.c_size_t)]
+            L.plv_trials_workspace_size.restype = C.c_int
+            L.plv_over_trials.argtypes = [P, C.c_int, C.POINTER(Trials), P, C.c_size_t, P]
+            L.plv_over_trials.restype = C.c_int
             L.plv_from_real.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64, C.POINTER(Band), C.c_int32,
                                         C.c_double, P, C.c_size_t, P]
             L.plv_from_real.restype = C.c_int

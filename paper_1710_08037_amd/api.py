@@ -157,6 +157,35 @@ def coherence(z, prec="split_bf16", window=None, want=ALL, want_g=False):
     return coherence_batch([z], prec, None if window is None else [window], want, want_g)[0]
 
 
+def over_trials(z, prec="split_bf16", window=None, want=ALL, want_g=False):
+    """Lachaux's PLV across trials (Eq. 1; matrix form Eq. 8): z is a complex
+    GPU tensor [ntr, n, t] of analytic signals (any strides: trial-major data
+    or a permuted view of signals x samples x trials).  For every time point
+    of `window` (default all), PLV / iPLV / ciPLV over the trials.
+    Returns a dict of [t1 - t0, n, n] tensors (and 'g' when want_g)."""
+    p = _prec_id(prec)
+    cd = torch.complex128 if p == 0 else torch.complex64
+    rd = torch.float64 if p == 0 else torch.float32
+    if z.dtype != cd:
+        raise TypeError("prec %s needs %s input, got %s" % (prec, cd, z.dtype))
+    if z.dim() != 3:
+        raise ValueError("z must be [ntr, n, t]")
+    ntr, n, t = z.shape
+    t0, t1 = (0, t) if window is None else (int(window[0]), int(window[1]))
+    dev = z.device
+    o = _outputs(n, t1 - t0, rd, cd, dev, want, want_g)
+    st = z.stride()
+    d = _abi.Trials(n, ntr, t, st[1], st[0], st[2], t0, t1, z.data_ptr(),
+                    *(_ptr(o[k]) for k in ("plv", "iplv", "ciplv", "g")))
+    ctx = context(dev)
+    nbytes = C.c_size_t(0)
+    _abi.check(_abi.lib().plv_trials_workspace_size(ctx.handle, p, C.byref(d), C.byref(nbytes)), ctx.handle)
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+    _abi.check(_abi.lib().plv_over_trials(ctx.handle, p, C.byref(d), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                          _stream(dev)), ctx.handle)
+    return o
+
+
 def from_real_batch(xs, fs, bands=None, prec="split_bf16", windows=None, want=ALL, want_g=False):
     """PLV/iPLV/ciPLV of real signals, the analytic signal formed on the GPU.
 

@@ -49,6 +49,36 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
     store4<MODE>(dst, a.plane_bytes, ur, ui);
 }
 
+// Across trials: thread (time point tau, signal i, trials k0..k0+3) reads
+// z(k, i, t0 + tau) -- consecutive threads take consecutive time points, so
+// the reads coalesce when samples are contiguous in time -- and stores the
+// four unit phasors at samples k0..k0+3 of row i of tau's planes (trials past
+// ntr are written as 0).
+template <int MODE>
+__global__ __launch_bounds__(256) void trial_planes_kernel(TrialArgs a)
+{
+    typedef typename std::conditional<MODE == M_F64, double, float>::type real_t;
+    typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
+    const int tau = blockIdx.x * 256 + threadIdx.x;
+    if (tau >= a.ntp)
+        return;
+    const int64_t i = a.row0 + blockIdx.y;
+    const int k0 = blockIdx.z * VEC;
+    auto src = gptr((const cplx_t *)a.in + i * a.ld + (a.t0 + tau) * a.sstride);
+    real_t ur[VEC], ui[VEC];
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) {
+        ur[v] = 0;
+        ui[v] = 0;
+        if (k0 + v < a.ntr) {
+            const cplx_t z = src[(int64_t)(k0 + v) * a.tstride];
+            unit_phasor(z.x, z.y, ur[v], ui[v]);
+        }
+    }
+    store4<MODE>(plane_at(a.u0 + (int64_t)tau * a.gstride, a.cstride, a.chunk, cbytes_of(MODE), i, k0),
+                 a.plane_bytes, ur, ui);
+}
+
 // One work-group per row: the largest |Re z| or |Im z| over the window, and
 // its exponent e (frexp convention, m = f 2^e with f in [0.5, 1)), give the
 // scale 2^-e.  A zero row gets 1.  The exponent is clamped to [-126, 126] so
@@ -83,6 +113,27 @@ __global__ __launch_bounds__(256) void row_scale_kernel(ScaleArgs a)
 }
 
 }  // namespace
+
+hipError_t launch_trial_planes(int mode, const TrialArgs &a, hipStream_t s)
+{
+    for (int r0 = 0; r0 < a.n; r0 += MAX_GRID_Y) {
+        TrialArgs b = a;
+        b.row0 = r0;
+        dim3 grid((a.ntp + 255) / 256, std::min(MAX_GRID_Y, a.n - r0), a.tpad / VEC);
+        switch (mode) {
+        case M_F64: trial_planes_kernel<M_F64><<<grid, 256, 0, s>>>(b); break;
+        case M_F32: trial_planes_kernel<M_F32><<<grid, 256, 0, s>>>(b); break;
+        case M_SPLIT: trial_planes_kernel<M_SPLIT><<<grid, 256, 0, s>>>(b); break;
+        case M_BF16: trial_planes_kernel<M_BF16><<<grid, 256, 0, s>>>(b); break;
+        case M_F16: trial_planes_kernel<M_F16><<<grid, 256, 0, s>>>(b); break;
+        default: return hipErrorInvalidValue;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_row_scale(bool f64, const ScaleArgs &a, hipStream_t s)
 {

@@ -412,7 +412,7 @@ static hipError_t launch_fft_setup(const Plan &plan, uint8_t *ws, hipStream_t s,
 // device tables, the front end (normalisation of analytic input, or the FFT
 // analytic signal of real input), the Gram kernel and the epilogue.
 static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_problem *probs, const plv_band *bands,
-                                  int nbands, double fs, uint8_t *ws, hipStream_t s)
+                                  int nbands, double fs, uint8_t *ws, hipStream_t s, const plv_trials *tr = nullptr)
 {
     const int mode = plan.mode;
     const bool real = plan.op == PLV_OP_FROM_REAL;
@@ -469,7 +469,31 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
     } else {
         StageTimer tm(ctx, PLV_STAGE_NORMALISE, s);
         const bool coh = plan.op == PLV_OP_COHERENCE;
+        if (tr) {
+            // across trials: one gather launch fills every time point's planes
+            const GramPlan &g0 = plan.grams[0];
+            TrialArgs ta{};
+            ta.in = tr->in;
+            ta.ld = tr->ld;
+            ta.tstride = tr->tstride;
+            ta.sstride = tr->sstride;
+            ta.t0 = tr->t0;
+            ta.n = (int32_t)tr->n;
+            ta.ntr = (int32_t)tr->ntr;
+            ta.ntp = (int32_t)plan.grams.size();
+            ta.u0 = ws + g0.u_off;
+            ta.gstride = plan.grams.size() > 1 ? (int64_t)(plan.grams[1].u_off - g0.u_off) : 0;
+            ta.plane_bytes = (int64_t)g0.plane_bytes;
+            ta.cstride = (int64_t)g0.npad * g0.chunk * cbytes_of(mode);
+            ta.chunk = g0.chunk;
+            ta.tpad = g0.tpad;
+            if ((e = launch_trial_planes(mode, ta, s)) != hipSuccess)
+                return hip_fail(ctx, e, "trial planes kernel launch");
+            tm.launched();
+        }
         for (const GramPlan &gp : plan.grams) {
+            if (tr)
+                break;
             const plv_problem &p = probs[gp.prob];
             if (coh) {
                 ScaleArgs sa{};
@@ -570,6 +594,86 @@ plv_status plv_from_analytic(plv_ctx *ctx, plv_prec prec, const plv_problem *pro
     if (st != PLV_OK)
         return st;
     return enqueue_forward(ctx, plan, probs, nullptr, 1, 0.0, (uint8_t *)ws, (hipStream_t)stream);
+}
+
+// Across trials: one Gram problem per time point (rows = signals, samples =
+// trials), described to the planner as problems whose input is never read by
+// the per-problem normalisation (the gather kernel fills their planes).
+static plv_status trials_problems(const plv_trials *p, plv_prec prec, std::vector<plv_problem> &probs,
+                                  std::string &why)
+{
+    if (!p) {
+        why = "trials descriptor is NULL";
+        return PLV_ERR_INVALID_ARG;
+    }
+    const int64_t t1 = p->t1 == 0 ? p->t : p->t1;
+    if (p->n < 1 || p->n > (1 << 20) || p->ntr < 1 || p->ntr > (1 << 17) || p->t < 1) {
+        char b[160];
+        snprintf(b, sizeof b, "need 1 <= n <= 2^20, 1 <= ntr <= 2^17, t >= 1 (n = %lld, ntr = %lld, t = %lld)",
+                 (long long)p->n, (long long)p->ntr, (long long)p->t);
+        why = b;
+        return PLV_ERR_INVALID_ARG;
+    }
+    if (p->ld < 1 || p->tstride < 1 || p->sstride < 1) {
+        why = "strides must be >= 1";
+        return PLV_ERR_INVALID_ARG;
+    }
+    if (p->t0 < 0 || t1 <= p->t0 || t1 > p->t || t1 - p->t0 > (1 << 24)) {
+        char b[160];
+        snprintf(b, sizeof b, "need 0 <= t0 < t1 <= t and at most 2^24 time points (t0 = %lld, t1 = %lld)",
+                 (long long)p->t0, (long long)t1);
+        why = b;
+        return PLV_ERR_INVALID_ARG;
+    }
+    const size_t esz = prec == PLV_PREC_F64 ? 8 : 4;
+    const size_t nn = (size_t)p->n * (size_t)p->n;
+    probs.assign((size_t)(t1 - p->t0), plv_problem{});
+    for (size_t k = 0; k < probs.size(); ++k) {
+        plv_problem &q = probs[k];
+        q.n = p->n;
+        q.t = p->ntr;
+        q.ld = p->ntr;
+        q.in = p->in;
+        q.plv = p->plv ? (uint8_t *)p->plv + k * nn * esz : nullptr;
+        q.iplv = p->iplv ? (uint8_t *)p->iplv + k * nn * esz : nullptr;
+        q.ciplv = p->ciplv ? (uint8_t *)p->ciplv + k * nn * esz : nullptr;
+        q.g = p->g ? (uint8_t *)p->g + k * nn * 2 * esz : nullptr;
+    }
+    return PLV_OK;
+}
+
+plv_status plv_trials_workspace_size(const plv_ctx *ctx, plv_prec prec, const plv_trials *p, size_t *bytes)
+{
+    if (!bytes)
+        return PLV_ERR_INVALID_ARG;
+    *bytes = 0;
+    std::vector<plv_problem> probs;
+    std::string why;
+    plv_status st = trials_problems(p, prec, probs, why);
+    if (st == PLV_OK)
+        return plv_workspace_size(ctx, PLV_OP_FROM_ANALYTIC, prec, probs.data(), (int64_t)probs.size(), nullptr, 1,
+                                  bytes);
+    if (ctx)
+        const_cast<plv_ctx *>(ctx)->err = why;
+    return st;
+}
+
+plv_status plv_over_trials(plv_ctx *ctx, plv_prec prec, const plv_trials *p, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    if (!ctx)
+        return PLV_ERR_INVALID_ARG;
+    std::vector<plv_problem> probs;
+    std::string why;
+    plv_status st = trials_problems(p, prec, probs, why);
+    if (st != PLV_OK)
+        return fail(ctx, st, "%s", why.c_str());
+    Plan plan;
+    st = begin(ctx, PLV_OP_FROM_ANALYTIC, prec, probs.data(), (int64_t)probs.size(), nullptr, 1, ws, ws_bytes,
+               plan);
+    if (st != PLV_OK)
+        return st;
+    return enqueue_forward(ctx, plan, probs.data(), nullptr, 1, 0.0, (uint8_t *)ws, (hipStream_t)stream, p);
 }
 
 plv_status plv_coherence(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob, void *ws,

@@ -130,6 +130,19 @@ struct NormArgs {
     const double *scale;  // coherency: per-row power-of-two scale (no unit normalisation), else nullptr
 };
 
+// Across trials: one launch fills the phasor planes of every time point's
+// Gram problem (rows = signals, samples = trials).
+struct TrialArgs {
+    const void *in;
+    int64_t ld, tstride, sstride, t0;  // complex elements
+    int32_t n, ntr, ntp;               // signals, trials, time points
+    int32_t row0;                      // first signal of this launch (signals run on blockIdx.y)
+    uint8_t *u0;                       // planes of time point 0
+    int64_t gstride;                   // bytes from one time point's planes to the next
+    int64_t plane_bytes, cstride;
+    int32_t chunk, tpad;
+};
+
 // Coherency: per-row scale 2^-e with e the exponent of the row's largest
 // component over the window, so scaled rows peak in [0.5, 1).
 struct ScaleArgs {
@@ -232,6 +245,7 @@ hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s);
 hipError_t launch_herk(int mode, const HerkArgs &a, int nwg, hipStream_t s);
 hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, hipStream_t s);
 hipError_t launch_row_scale(bool f64, const ScaleArgs &a, hipStream_t s);
+hipError_t launch_trial_planes(int mode, const TrialArgs &a, hipStream_t s);
 // d[i] = fixed-order sum over slots of the diagonal entries of G's partials
 hipError_t launch_diag(int mode, const GramDesc &g, hipStream_t s);
 // Occupancy (work-groups per CU) of the Gram kernel of `mode`.
