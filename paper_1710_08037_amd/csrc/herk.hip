@@ -21,13 +21,17 @@
 // FP32 and FP64 use v_mfma_{f32_16x16x4f32,f64_16x16x4f64} on the re and im
 // lanes separately (4 samples per instruction, 4 products).
 //
-// Tiling (all modes): 256 threads = 4 waves in 2 x 2, each wave a
-// (BM/2) x (BM/2) sub-tile made of 16 x 16 MFMA blocks.  Each K-stage holds
-// 64 bytes per row (16 / 8 / 4 samples for 16-bit / f32 / f64) of the row
-// panel I and the column panel J.  They move global -> LDS directly
-// (global_load_lds_dwordx4, no staging registers) into a ring of NS stages,
-// with the 16-byte positions of each 64-byte LDS row XOR-swizzled by row.
-// A diagonal tile (I == J) loads one panel and uses it as both operands.
+// Tiling (all modes): 512 threads = 8 waves in two groups of four; within a
+// group the waves sit 2 x 2, each one a (BM/2) x (BM/2) sub-tile made of
+// 16 x 16 MFMA blocks, and the two groups take alternate K-units and add
+// their sums at the end.  Each K-stage holds 64 bytes per row (16 / 8 / 4
+// samples for 16-bit / f32 / f64) of the row panel I and the column panel J.
+// They move global -> LDS directly (global_load_lds_dwordx4, no staging
+// registers) into a ring of NS stages, with the 16-byte positions of each
+// 64-byte LDS row XOR-swizzled by row.  A diagonal tile (I == J) loads one
+// panel and uses it as both operands.  The groups ping-pong: in each barrier
+// interval one group reads a unit's fragments from LDS into registers while
+// the other runs the MFMAs of the unit it read in the interval before.
 //
 // Work-groups are handed out XCD-aware: the hardware deals work-group ids
 // round-robin over the 8 XCDs, so ids are remapped to give each XCD a
@@ -46,8 +50,9 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int RB = 64;  // bytes of one row staged per K-stage, per plane
 
-// LDS ring depth per mode: (NS - 1) stages of loads are in flight while one
-// is consumed.  Stage bytes = planes x 2 panels x BM rows x 64 B.
+// LDS ring depth per mode, in stages of planes x 2 panels x BM rows x 64 B.
+// With units of SPI stages the ring holds NS / SPI units: while one is read,
+// the loads of the next NS / SPI - 2 are in flight and one more is issued.
 template <int MODE>
 struct Ring {
     static constexpr int BM = tile_of(MODE);
@@ -124,6 +129,33 @@ __device__ inline void wait_vm()
     __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// s_waitcnt lgkmcnt(0) only (vmcnt and expcnt left at their maxima).
+__device__ inline void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4)); }
+
+// Operand fragments of one unit of SPI K-stages, for one wave's
+// (BM/2) x (BM/2) sub-tile: the row panel's blocks (a) and the column
+// panel's blocks (b).  The 16-bit modes take two stages per unit so that a
+// unit's MFMA work stays long next to the barrier that separates units.
+template <int MODE>
+struct Frags {
+    static constexpr int NB = tile_of(MODE) / 32;
+    static constexpr int PL = planes_of(MODE);
+    static constexpr int SPI = (MODE == M_BF16 || MODE == M_F16) ? 2 : 1;
+    u32x4 a[SPI][PL][NB], b[SPI][PL][NB];
+};
+template <>
+struct Frags<M_F32> {
+    static constexpr int NB = tile_of(M_F32) / 32;
+    static constexpr int SPI = 1;
+    float2 a[2][NB], b[2][NB];  // two K-steps of 4 samples
+};
+template <>
+struct Frags<M_F64> {
+    static constexpr int NB = tile_of(M_F64) / 32;
+    static constexpr int SPI = 1;
+    double2 a[NB], b[NB];
+};
+
 // Work-group barrier without a memory fence.  __syncthreads() would make
 // every wave drain all of its in-flight loads first (vmcnt(0)), which would
 // collapse the ring to one stage; each wave instead waits for its own loads
@@ -150,12 +182,17 @@ __device__ inline void herk_tile(const GramDesc &d, const uint8_t *ua, const uin
 {
     typedef Ring<MODE> R;
     constexpr int BM = R::BM, NB = BM / 32, PL = R::PL, PANEL = R::PANEL, STAGE = R::STAGE, NS = R::NS;
-    constexpr int NR = NS / 2;                    // rounds held by the ring (2 stages per round)
     constexpr int CB = cbytes_of(MODE);
     constexpr int BLKS = PANEL / 1024;            // 1 KB load blocks per panel and plane
     constexpr int SLOTS = PL * (DIAG ? 1 : 2) * BLKS;  // load blocks per stage
-    static_assert(SLOTS % WAVES == 0 || SLOTS < WAVES, "load blocks per wave");
-    constexpr int LPS = (SLOTS + WAVES - 1) / WAVES;    // loads per stage per wave (last ones may idle)
+    // Who issues a unit's loads.  16-bit modes: only the group that reads in
+    // the interval whose head issues them, so the computing group's MFMAs do
+    // not queue behind a burst of loads (measured: 13-22% faster).  FP32 and
+    // FP64, whose intervals are long, spread the loads over all waves.
+    constexpr bool ONE_GROUP = (CB == 4);
+    constexpr int IW = ONE_GROUP ? WAVES / 2 : WAVES;   // issuing waves
+    static_assert(SLOTS % IW == 0 || SLOTS < IW, "load blocks per wave");
+    constexpr int LPS = (SLOTS + IW - 1) / IW;          // loads per stage per issuing wave (last ones may idle)
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -174,7 +211,7 @@ __device__ inline void herk_tile(const GramDesc &d, const uint8_t *ua, const uin
         uint8_t *base = smem + buf * STAGE;
 #pragma unroll
         for (int q = 0; q < LPS; ++q) {
-            const int slot = wave + WAVES * q;   // wave-uniform
+            const int slot = (ONE_GROUP ? wq : wave) + IW * q;  // wave-uniform
             if (slot < SLOTS) {
                 const int blk = slot % BLKS;
                 const int pp = slot / BLKS;      // plane * (1 or 2) + panel
@@ -193,108 +230,154 @@ __device__ inline void herk_tile(const GramDesc &d, const uint8_t *ua, const uin
     const int arow = (wm * (BM / 2) + fr) * RB;
     const int brow = (wn * (BM / 2) + fr) * RB + (DIAG ? 0 : PANEL);
 
-    auto compute = [&](int buf) {
-        const uint8_t *S = smem + buf * STAGE;
-        if constexpr (CB == 4) {
-            // 16 samples = one K' = 32 step of v_mfma_*_16x16x32
-            const int off = (((lane >> 4) ^ swz(fr)) * 16);
-            u32x4 vb[PL][NB];
+    // One unit = SPI consecutive stages.  A wave reads all operand fragments
+    // of a unit from LDS into registers (Frags), then runs that unit's MFMAs
+    // from registers in the next interval.
+    typedef Frags<MODE> F;
+    constexpr int SPI = F::SPI;
+    constexpr int NU = NS / SPI;                  // units held by the ring
+    constexpr int LPU = SPI * LPS;                // loads per unit per wave
+    F fg;
+    auto issue_unit = [&](int u) {
 #pragma unroll
-            for (int p = 0; p < PL; ++p)
+        for (int s = 0; s < SPI; ++s)
+            issue(u * SPI + s, (u % NU) * SPI + s);
+    };
+
+    auto read_frags = [&](int u) {
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    vb[p][b] = *(const u32x4 *)(S + p * 2 * PANEL + brow + b * 16 * RB + off);
+        for (int s = 0; s < SPI; ++s) {
+            const uint8_t *S = smem + ((u % NU) * SPI + s) * STAGE;
+            if constexpr (CB == 4) {
+                const int off = (((lane >> 4) ^ swz(fr)) * 16);
 #pragma unroll
-            for (int a = 0; a < NB; ++a) {
-                u32x4 va[PL], vq[PL];
-#pragma unroll
-                for (int p = 0; p < PL; ++p) {
-                    va[p] = *(const u32x4 *)(S + p * 2 * PANEL + arow + a * 16 * RB + off);
-                    vq[p] = swap_neg(va[p]);
-                }
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    re[a][b] = mfma16<MODE>(va[0], vb[0][b], re[a][b]);
-                    im[a][b] = mfma16<MODE>(vq[0], vb[0][b], im[a][b]);
-                    if constexpr (PL == 2) {
-                        re[a][b] = mfma16<MODE>(va[0], vb[1][b], re[a][b]);
-                        im[a][b] = mfma16<MODE>(vq[0], vb[1][b], im[a][b]);
-                        re[a][b] = mfma16<MODE>(va[1], vb[0][b], re[a][b]);
-                        im[a][b] = mfma16<MODE>(vq[1], vb[0][b], im[a][b]);
-                    }
-                }
-            }
-        } else if constexpr (CB == 8) {
-            // FP32: 8 samples = 2 steps of 4; one sample (re, im) per lane
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const int off = (((ks * 2 + (lane >> 5)) ^ swz(fr)) * 16) + ((lane >> 4) & 1) * 8;
-                float2 vb[NB];
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    vb[b] = *(const float2 *)(S + brow + b * 16 * RB + off);
-#pragma unroll
-                for (int a = 0; a < NB; ++a) {
-                    const float2 va = *(const float2 *)(S + arow + a * 16 * RB + off);
+                for (int p = 0; p < PL; ++p)
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb[b].x, re[a][b], 0, 0, 0);
-                        re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb[b].y, re[a][b], 0, 0, 0);
-                        im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb[b].x, im[a][b], 0, 0, 0);
-                        im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-va.x, vb[b].y, im[a][b], 0, 0, 0);
+                        fg.a[s][p][b] = *(const u32x4 *)(S + p * 2 * PANEL + arow + b * 16 * RB + off);
+                        fg.b[s][p][b] = *(const u32x4 *)(S + p * 2 * PANEL + brow + b * 16 * RB + off);
+                    }
+            } else if constexpr (CB == 8) {
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const int off = (((ks * 2 + (lane >> 5)) ^ swz(fr)) * 16) + ((lane >> 4) & 1) * 8;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        fg.a[ks][b] = *(const float2 *)(S + arow + b * 16 * RB + off);
+                        fg.b[ks][b] = *(const float2 *)(S + brow + b * 16 * RB + off);
                     }
                 }
-            }
-        } else {
-            // FP64: 4 samples = 1 step of 4; one sample (re, im) per lane
-            const int off = (((lane >> 4) ^ swz(fr)) * 16);
-            double2 vb[NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                vb[b] = *(const double2 *)(S + brow + b * 16 * RB + off);
-#pragma unroll
-            for (int a = 0; a < NB; ++a) {
-                const double2 va = *(const double2 *)(S + arow + a * 16 * RB + off);
+            } else {
+                const int off = (((lane >> 4) ^ swz(fr)) * 16);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.x, vb[b].x, re[a][b], 0, 0, 0);
-                    re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, vb[b].y, re[a][b], 0, 0, 0);
-                    im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, vb[b].x, im[a][b], 0, 0, 0);
-                    im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-va.x, vb[b].y, im[a][b], 0, 0, 0);
+                    fg.a[b] = *(const double2 *)(S + arow + b * 16 * RB + off);
+                    fg.b[b] = *(const double2 *)(S + brow + b * 16 * RB + off);
                 }
             }
         }
     };
 
-    // ---- K loop.  Stages go in rounds of two: group 0 takes the even stage,
-    // group 1 the odd one, so two waves share each SIMD.  The ring holds NR
-    // rounds; each round: wait for this round's own loads, one barrier
-    // (everyone's loads landed, everyone is done with the previous round's
-    // buffers), refill those buffers NR - 1 rounds ahead, compute.
-    const int nround = (nst + 1) / 2;
+    auto mma = [&]() {
+        if constexpr (CB == 4) {
+            // 16 samples per stage = one K' = 32 step of v_mfma_*_16x16x32
 #pragma unroll
-    for (int i = 0; i < NS - 2; ++i)
-        if (i < nst)
-            issue(i, i);
-    for (int r = 0; r < nround; ++r) {
-        // Loads issued after this round's: rounds r+1 .. r+NR-2, LPS per
-        // stage per wave (each wave issues exactly LPS or none).  Waiting down
-        // to that many is exact only when all of those stages exist;
-        // otherwise wait for everything.
-        if (NR > 2 && 2 * (r + NR - 2) + 1 < nst)
-            wait_vm<(NS - 4) * LPS>();
+            for (int s = 0; s < SPI; ++s)
+#pragma unroll
+                for (int a = 0; a < NB; ++a) {
+                    u32x4 vq[PL];
+#pragma unroll
+                    for (int p = 0; p < PL; ++p)
+                        vq[p] = swap_neg(fg.a[s][p][a]);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        re[a][b] = mfma16<MODE>(fg.a[s][0][a], fg.b[s][0][b], re[a][b]);
+                        im[a][b] = mfma16<MODE>(vq[0], fg.b[s][0][b], im[a][b]);
+                        if constexpr (PL == 2) {
+                            re[a][b] = mfma16<MODE>(fg.a[s][0][a], fg.b[s][1][b], re[a][b]);
+                            im[a][b] = mfma16<MODE>(vq[0], fg.b[s][1][b], im[a][b]);
+                            re[a][b] = mfma16<MODE>(fg.a[s][1][a], fg.b[s][0][b], re[a][b]);
+                            im[a][b] = mfma16<MODE>(vq[1], fg.b[s][0][b], im[a][b]);
+                        }
+                    }
+                }
+        } else if constexpr (CB == 8) {
+            // FP32: 8 samples = 2 steps of 4; one sample (re, im) per lane
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+                for (int a = 0; a < NB; ++a) {
+                    const float2 va = fg.a[ks][a];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const float2 vb = fg.b[ks][b];
+                        re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.x, vb.x, re[a][b], 0, 0, 0);
+                        re[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb.y, re[a][b], 0, 0, 0);
+                        im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(va.y, vb.x, im[a][b], 0, 0, 0);
+                        im[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-va.x, vb.y, im[a][b], 0, 0, 0);
+                    }
+                }
+        } else {
+            // FP64: 4 samples = 1 step of 4; one sample (re, im) per lane
+#pragma unroll
+            for (int a = 0; a < NB; ++a) {
+                const double2 va = fg.a[a];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const double2 vb = fg.b[b];
+                    re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.x, vb.x, re[a][b], 0, 0, 0);
+                    re[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, vb.y, re[a][b], 0, 0, 0);
+                    im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(va.y, vb.x, im[a][b], 0, 0, 0);
+                    im[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-va.x, vb.y, im[a][b], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    // ---- K loop, ping-pong between the two wave groups (one wave of each
+    // per SIMD).  In interval k group k % 2 reads unit k's fragments from LDS
+    // while the other group runs the MFMAs of unit k - 1 from the fragments
+    // it read in interval k - 1, so the matrix cores of a SIMD are fed by one
+    // wave while the other waits on LDS.  Every interval opens with the same
+    // head in every wave: wait for this wave's own loads of unit k, one
+    // barrier (unit k landed for every wave; unit k - 1's fragments are in
+    // registers, so its buffers are free), refill those buffers with unit
+    // k + NU - 1.  Group 1 sits out interval 0; each loop trip is then one
+    // read interval and one compute interval of the wave's own group.
+    const int nu = nst / SPI;
+    // Unit j is loaded at the head of interval j - NU + 1 (before the loop for
+    // j < NU - 1): by every wave, or with ONE_GROUP by group (j + NU + 1) % 2,
+    // the one reading in that interval.  Each wave issues exactly LPU loads
+    // per unit it takes part in, or none.  After unit k a wave then has at
+    // most W units outstanding, none of them beyond unit k + LAST.
+    constexpr int W = ONE_GROUP ? (NU - 2) / 2 : NU - 2;
+    constexpr int LAST = ONE_GROUP ? 2 * W : W;
+    auto head = [&](int k) {
+        if (k + LAST < nu)
+            wait_vm<W * LPU>();
         else
             wait_vm<0>();
         stage_barrier();
-        const int nxt = r + NR - 1;
+        if (k + NU - 1 < nu && (!ONE_GROUP || (k & 1) == grp))
+            issue_unit(k + NU - 1);
+    };
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-            if (2 * nxt + h < nst)
-                issue(2 * nxt + h, (2 * nxt + h) % NS);
-        const int st = 2 * r + grp;
-        if (st < nst)
-            compute(st % NS);
+    for (int v = 0; v < NU - 1; ++v)
+        if (v < nu && (!ONE_GROUP || ((v + NU + 1) & 1) == grp))
+            issue_unit(v);
+    int k = grp;
+    if (grp == 1)
+        head(0);
+    for (; k < nu; k += 2) {
+        head(k);
+        read_frags(k);
+        wait_lgkm0();  // fragments in registers before the next barrier frees the buffers
+        head(k + 1);
+        mma();
     }
+    if (k == nu + 1)
+        return;  // the last trip ran the head of interval nu
+    head(nu);    // k == nu: interval nu is still open (the other group's last compute)
 }
 
 // Folds group 1's accumulators into group 0's through LDS (after the K loop).
