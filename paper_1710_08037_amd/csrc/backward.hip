@@ -20,7 +20,7 @@ constexpr int TB = 64;  // transpose block: 64 signals x 64 samples
 
 // W[s][k] = conj(u_k(s)) for s < tw, k < kpad (0 for k >= n): rows are
 // samples, K runs over signals.  Reads z coalesced along samples, writes W
-// coalesced along signals, through an LDS tile.
+// in groups of 4 signals (one store4 each), through an LDS tile.
 template <int MODE>
 __global__ __launch_bounds__(256) void planes_t_kernel(BwdPlanesArgs a)
 {
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void planes_t_kernel(BwdPlanesArgs a)
             ur[v] = tre[kq + v][ss];
             ui[v] = tim[kq + v][ss];
         }
-        store4<MODE>(a.w + ((int64_t)s * a.kpad + k0 + kq) * cbytes_of(MODE), a.plane_bytes, ur, ui);
+        store4<MODE>(a.w + plane_off(a.rows, cbytes_of(MODE), s, k0 + kq), a.plane_bytes, ur, ui);
     }
 }
 
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void metric_adjoint_kernel(BwdMetricArgs a)
         hr[v] = (R)(gr * a.inv_t);
         hi[v] = (R)((i < j ? gm : -gm) * a.inv_t);
     }
-    store4<MODE>(a.h + (i * a.kpad + j0) * cbytes_of(MODE), a.plane_bytes, hr, hi);
+    store4<MODE>(a.h + plane_off(a.rows, cbytes_of(MODE), i, j0), a.plane_bytes, hr, hi);
 }
 
 // zbar = i Im(conj(u) ubar) u / |z| on the window; for the full-row form

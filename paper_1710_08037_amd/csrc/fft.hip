@@ -415,7 +415,7 @@ __device__ inline void store_band(int mode, const GramDesc &g, const HilbertProb
                 unit_phasor(z.x, z.y, ur[v], ui[v]);
             }
         }
-        store4_mode<R>(mode, plane_at((uint8_t *)g.u, g.cstride, (int)g.ldu, cbytes_of(mode), row, s0),
+        store4_mode<R>(mode, plane_at((uint8_t *)g.u, g.cstride, g.chunk, g.npad, cbytes_of(mode), row, s0),
                        g.plane_bytes, ur, ui);
     }
 }
@@ -478,7 +478,7 @@ __device__ inline void direct_band(int mode, const GramDesc &g, const HilbertPro
                 if (s0 + v < hp.tw)
                     unit_phasor(z[v].x, z[v].y, ur[v], ui[v]);
             }
-            store4_mode<R>(mode, plane_at((uint8_t *)g.u, g.cstride, (int)g.ldu, cbytes_of(mode), row, s0),
+            store4_mode<R>(mode, plane_at((uint8_t *)g.u, g.cstride, g.chunk, g.npad, cbytes_of(mode), row, s0),
                            g.plane_bytes, ur, ui);
         }
     }

@@ -201,13 +201,15 @@ __device__ inline void herk_tile(const GramDesc &d, const uint8_t *ua, const uin
 
     // ---- direct global -> LDS loads: lane L of a 1 KB block stages row L/4,
     // LDS position L%4, which holds the row's segment (L%4) ^ swz(L/4).
-    const int64_t pitch = d.ldu * CB;
+    // Stage-major planes: K-stage st of row r sits at st * rows * RB + r * RB,
+    // so one load block (16 rows) is one contiguous kilobyte.
+    const int64_t sa = (int64_t)d.npad * RB;                              // A: npad rows
+    const int64_t sb = d.ub ? (int64_t)d.ntile_b * BM * RB : sa;         // B: its own row count
     const int lr = lane >> 2;
-    const uint32_t voff = (uint32_t)(lr * pitch) + (uint32_t)(((lane & 3) ^ swz(lr)) * 16);
-    const uint8_t *gA = ua + (int64_t)I * BM * pitch;
-    const uint8_t *gB = ub + (int64_t)J * BM * pitch;
+    const uint32_t voff = (uint32_t)(lr * RB) + (uint32_t)(((lane & 3) ^ swz(lr)) * 16);
+    const uint8_t *gA = ua + (int64_t)I * BM * RB;
+    const uint8_t *gB = ub + (int64_t)J * BM * RB;
     auto issue = [&](int st, int buf) {
-        const int64_t koff = (int64_t)st * RB;
         uint8_t *base = smem + buf * STAGE;
 #pragma unroll
         for (int q = 0; q < LPS; ++q) {
@@ -217,7 +219,7 @@ __device__ inline void herk_tile(const GramDesc &d, const uint8_t *ua, const uin
                 const int pp = slot / BLKS;      // plane * (1 or 2) + panel
                 const int p = DIAG ? pp : (pp >> 1);
                 const int isb = DIAG ? 0 : (pp & 1);
-                const uint8_t *g = (isb ? gB : gA) + p * d.plane_bytes + (int64_t)blk * 16 * pitch + koff;
+                const uint8_t *g = (isb ? gB + st * sb : gA + st * sa) + p * d.plane_bytes + blk * 16 * RB;
                 __builtin_amdgcn_global_load_lds((gvoid *)(g + voff),
                                                  (lds_void *)(base + p * 2 * PANEL + isb * PANEL + blk * 1024),
                                                  16, 0, 0);

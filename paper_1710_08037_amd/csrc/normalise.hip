@@ -9,8 +9,10 @@
 // / f64, or as two bf16 planes hi = rn(u), lo = rn(u - hi) for the split mode.
 // Samples past the window are written as 0 + 0i up to the padded length.
 //
-// HBM-bound: each thread moves 4 consecutive samples (32 B in for c64, 16 or
-// 32 B out), rows map to blockIdx.y so every access is contiguous.
+// HBM-bound: each thread moves 4 consecutive samples (32 B in for c64, 16 to
+// 64 B out).  A block covers 16 samples of 64 consecutive rows, so a wave
+// reads whole 128-byte runs (c64) of 16 rows and writes, per plane stage,
+// one contiguous run of 16 rows of the stage-major planes.
 #include "phasor.h"
 
 namespace plv {
@@ -18,26 +20,57 @@ namespace {
 
 constexpr int VEC = 4;  // samples per thread
 
+// A block covers SPB = 16 consecutive samples (one to four plane stages) of
+// RPB = 64 consecutive rows: 4 threads per row, each 4 samples.
+struct NormShape {
+    static constexpr int SPB = 16;          // samples per block row
+    static constexpr int QPS = SPB / VEC;   // threads per row
+    static constexpr int RPB = 256 / QPS;   // rows per block
+};
+
 template <int MODE>
 __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
 {
-    const int row = a.row0 + blockIdx.y;
-    const int s0 = (blockIdx.x * 256 + threadIdx.x) * VEC;
-    if (s0 >= a.tpad)
+    typedef NormShape S;
+    const int row = a.row0 + blockIdx.y * S::RPB + threadIdx.x / S::QPS;
+    const int s0 = blockIdx.x * S::SPB + (threadIdx.x % S::QPS) * VEC;
+    if (row >= a.n || s0 >= a.tpad)
         return;
-    uint8_t *dst = plane_at(a.u, a.cstride, a.chunk, cbytes_of(MODE), row, s0);  // 4 samples never straddle chunks
+    // 4 samples never straddle a stage or a chunk (both multiples of 4)
+    uint8_t *dst = plane_at(a.u, a.cstride, a.chunk, a.rows, cbytes_of(MODE), row, s0);
     typedef typename std::conditional<MODE == M_F64, double, float>::type real_t;
     typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
     auto src = gptr((const cplx_t *)a.in + (int64_t)row * a.ld + a.t0);
     real_t ur[VEC], ui[VEC];
     const real_t sc = a.scale ? (real_t)a.scale[row] : (real_t)1;  // a power of two: exact
+    cplx_t zin[VEC];
+    if constexpr (MODE != M_F64) {
+        // complex64 rows starting on a 16-byte boundary: the 4 samples as two
+        // 16-byte loads (half the load instructions of per-sample loads)
+        if ((((int64_t)row * a.ld + a.t0) & 1) == 0 && s0 + VEC <= a.tw) {
+            auto q = (const PLV_GLOBAL vf4 *)(src + s0);
+            const vf4 q0 = q[0], q1 = q[1];
+            zin[0] = vf2{q0.x, q0.y};
+            zin[1] = vf2{q0.z, q0.w};
+            zin[2] = vf2{q1.x, q1.y};
+            zin[3] = vf2{q1.z, q1.w};
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                zin[v] = s0 + v < a.tw ? src[s0 + v] : cplx_t{0, 0};
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+            zin[v] = s0 + v < a.tw ? src[s0 + v] : cplx_t{0, 0};
+    }
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         const int s = s0 + v;
         ur[v] = 0;
         ui[v] = 0;
         if (s < a.tw) {
-            cplx_t z = src[s];
+            cplx_t z = zin[v];
             if (a.scale) {
                 ur[v] = z.x * sc;
                 ui[v] = z.y * sc;
@@ -75,7 +108,7 @@ __global__ __launch_bounds__(256) void trial_planes_kernel(TrialArgs a)
             unit_phasor(z.x, z.y, ur[v], ui[v]);
         }
     }
-    store4<MODE>(plane_at(a.u0 + (int64_t)tau * a.gstride, a.cstride, a.chunk, cbytes_of(MODE), i, k0),
+    store4<MODE>(plane_at(a.u0 + (int64_t)tau * a.gstride, a.cstride, a.chunk, a.rows, cbytes_of(MODE), i, k0),
                  a.plane_bytes, ur, ui);
 }
 
@@ -146,25 +179,40 @@ hipError_t launch_row_scale(bool f64, const ScaleArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s)
+namespace {
+
+template <int MODE>
+hipError_t normalise_rows(const NormArgs &a, hipStream_t s)
 {
-    for (int r0 = 0; r0 < a.n; r0 += MAX_GRID_Y) {
+    typedef NormShape S;
+    const int64_t span = (int64_t)MAX_GRID_Y * S::RPB;  // rows per launch
+    for (int64_t r0 = 0; r0 < a.n; r0 += span) {
         NormArgs b = a;
-        b.row0 = r0;
-        dim3 grid((a.tpad + 256 * VEC - 1) / (256 * VEC), std::min(MAX_GRID_Y, a.n - r0));
-        switch (mode) {
-        case M_F64: normalise_kernel<M_F64><<<grid, 256, 0, s>>>(b); break;
-        case M_F32: normalise_kernel<M_F32><<<grid, 256, 0, s>>>(b); break;
-        case M_SPLIT: normalise_kernel<M_SPLIT><<<grid, 256, 0, s>>>(b); break;
-        case M_BF16: normalise_kernel<M_BF16><<<grid, 256, 0, s>>>(b); break;
-        case M_F16: normalise_kernel<M_F16><<<grid, 256, 0, s>>>(b); break;
-        default: return hipErrorInvalidValue;
-        }
+        b.row0 = (int32_t)r0;
+        const int64_t nr = std::min<int64_t>(span, a.n - r0);
+        dim3 grid(a.tpad / S::SPB, (unsigned)((nr + S::RPB - 1) / S::RPB));
+        normalise_kernel<MODE><<<grid, 256, 0, s>>>(b);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
     }
     return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s)
+{
+    if (a.tpad % 32 != 0)
+        return hipErrorInvalidValue;  // tpad is a multiple of PLV_KGRAN, so of every stage width
+    switch (mode) {
+    case M_F64: return normalise_rows<M_F64>(a, s);
+    case M_F32: return normalise_rows<M_F32>(a, s);
+    case M_SPLIT: return normalise_rows<M_SPLIT>(a, s);
+    case M_BF16: return normalise_rows<M_BF16>(a, s);
+    case M_F16: return normalise_rows<M_F16>(a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace plv

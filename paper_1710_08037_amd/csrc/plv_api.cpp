@@ -486,6 +486,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             ta.plane_bytes = (int64_t)g0.plane_bytes;
             ta.cstride = (int64_t)g0.npad * g0.chunk * cbytes_of(mode);
             ta.chunk = g0.chunk;
+            ta.rows = g0.npad;
             ta.tpad = g0.tpad;
             if ((e = launch_trial_planes(mode, ta, s)) != hipSuccess)
                 return hip_fail(ctx, e, "trial planes kernel launch");
@@ -518,6 +519,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             na.plane_bytes = (int64_t)gp.plane_bytes;
             na.cstride = (int64_t)gp.npad * gp.chunk * cbytes_of(mode);
             na.chunk = gp.chunk;
+            na.rows = gp.npad;
             na.tpad = gp.tpad;
             if ((e = launch_normalise(mode, na, s)) != hipSuccess)
                 return hip_fail(ctx, e, "normalise kernel launch");
@@ -772,6 +774,7 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
         pa.n = g.n;
         pa.tw = g.t;
         pa.kpad = g.kpad;
+        pa.rows = g.ntile_b * tile_of(mode);
         pa.w = ws + g.w_off;
         pa.plane_bytes = (int64_t)g.plane_bytes;
         if ((e = launch_planes_t(mode, pa, s)) != hipSuccess)
@@ -785,6 +788,7 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
         ma.n = g.n;
         ma.kpad = g.kpad;
         ma.inv_t = 1.0 / (double)g.t;
+        ma.rows = g.npad;
         ma.h = ws + g.u_off;
         ma.plane_bytes = (int64_t)g.plane_bytes;
         if ((e = launch_metric_adjoint(mode, ma, s)) != hipSuccess)

@@ -1,14 +1,15 @@
 // plv_internal.h -- descriptors shared by the host layer and the gfx950 kernels.
 //
 // Layout of the phasor planes U in the workspace (one "Gram problem" = one
-// problem x band): chunk-major.  The window, rounded up to tpad (a multiple
-// of PLV_KGRAN samples, zero-filled beyond the window: padding adds nothing to
-// G), is cut into K-chunks of `chunk` samples; chunk c of every row is stored
-// together as a block [npad][chunk] of interleaved complex phasors
-// u = z/|z| (Eq. 4), blocks cstride bytes apart.  A Gram work-group reads one
-// block, so its rows sit a chunk apart rather than a whole T apart (few pages
-// per panel).  Rows n..npad-1 are never written and only feed output entries
-// that are discarded; the tail of the last block past tpad is never touched.
+// problem x band): chunk blocks, stage-major inside.  The window, rounded up
+// to tpad (a multiple of PLV_KGRAN samples, zero-filled beyond the window:
+// padding adds nothing to G), is cut into K-chunks of `chunk` samples; chunk
+// c of every row is stored together as one block of interleaved complex
+// phasors u = z/|z| (Eq. 4), blocks cstride bytes apart.  Inside a block the
+// samples go in 64-byte stages, all npad rows of one stage back to back
+// (plane_off below), so each K-stage of a tile's row panel is one contiguous
+// run.  Rows n..npad-1 are never written and only feed output entries that
+// are discarded; the tail of the last block past tpad is never touched.
 //   Element per complex sample: 2 x bf16/f16 (4 B), 2 x f32 (8 B), 2 x f64 (16 B).
 //   PLV_PREC_SPLIT_BF16 has two such planes, hi then lo, plane_bytes apart.
 #pragma once
@@ -46,12 +47,24 @@ typedef uint32_t vu4 __attribute__((ext_vector_type(4)));
 
 enum Mode { M_F64 = 0, M_F32 = 1, M_SPLIT = 2, M_BF16 = 3, M_F16 = 4 };
 
-// Address of sample s of `row` in chunk-major phasor planes (plane 0);
-// cb bytes per complex element.
-__device__ inline uint8_t *plane_at(uint8_t *u, int64_t cstride, int chunk, int cb, int64_t row, int s)
+// Phasor planes, stage-major.  K (samples; signals in the backward's product
+// operands) is cut into blocks of `chunk`, block c starting c * cstride bytes
+// in.  Inside a block, a 64-byte stage holds SPS = 64 / cb consecutive
+// K-elements of one row, and the stages of all `rows` rows for the same K
+// range lie back to back: element (row, k) of a block is at
+// ((k / SPS) * rows + row) * 64 + (k % SPS) * cb.  A K-stage of 16 rows is
+// then one contiguous kilobyte, the unit the Gram kernel moves into LDS.
+__host__ __device__ inline int64_t plane_off(int64_t rows, int cb, int64_t row, int64_t k)
+{
+    const int lsps = cb == 4 ? 4 : (cb == 8 ? 3 : 2);  // log2(SPS)
+    return (((k >> lsps) * rows + row) << 6) + (k & ((1 << lsps) - 1)) * cb;
+}
+
+// Address of sample s of `row` in the planes (plane 0).
+__device__ inline uint8_t *plane_at(uint8_t *u, int64_t cstride, int chunk, int64_t rows, int cb, int64_t row, int s)
 {
     const int c = s < chunk ? 0 : s / chunk;  // single-chunk problems skip the division
-    return u + c * cstride + (row * chunk + (s - c * chunk)) * cb;
+    return u + c * cstride + plane_off(rows, cb, row, s - c * chunk);
 }
 
 // Tile edge of the Gram kernel for each mode (output tiles are BM x BM).
@@ -64,9 +77,8 @@ __host__ __device__ constexpr int planes_of(int mode) { return mode == M_SPLIT ?
 struct GramDesc {
     const uint8_t *u;     // plane 0
     int64_t plane_bytes;  // plane 1 = u + plane_bytes (split only)
-    int64_t ldu;          // row pitch of U in complex elements (= chunk)
     int64_t cstride;      // bytes from one chunk block to the next (0: one block)
-    int32_t n, npad;      // signals, rows rounded up to the tile
+    int32_t n, npad;      // signals, rows rounded up to the tile (the planes' row count)
     int32_t t, tpad;      // true window length (the 1/T), padded length
     int32_t ntile;        // tiles per side = npad / BM
     int32_t nupper;       // tiles with I <= J = ntile (ntile + 1) / 2
@@ -77,8 +89,9 @@ struct GramDesc {
     double *partial;      // [nslot][nupper][2][BM][BM] FP64 chunk sums (unused when fused)
     void *plv, *iplv, *ciplv, *g;  // outputs, [n][n] (g complex interleaved)
     // General product mode (used by the backward): C = A B^H over the full
-    // tile grid, A = the planes at u (rows n), B = the planes at ub (rows nb),
-    // same row pitch; C stored directly as complex (f32; f64 in F64 mode).
+    // tile grid, A = the planes at u (npad rows), B = the planes at ub
+    // (ntile_b * BM rows), one block of K = tpad each; C stored directly as
+    // complex (f32; f64 in F64 mode).
     const uint8_t *ub;    // B operand planes, nullptr in Gram mode
     int32_t nb, ntile_b;  // B rows, B tiles
     void *c;              // C [n][ldc] complex
@@ -123,10 +136,11 @@ struct NormArgs {
     int32_t n;            // rows
     uint8_t *u;           // plane 0
     int64_t plane_bytes;
-    int64_t cstride;      // chunk-major layout of the planes (see above)
+    int64_t cstride;      // stage-major layout of the planes (see plane_off)
     int32_t chunk;
+    int32_t rows;         // the planes' row count (npad)
     int32_t tpad;
-    int32_t row0;         // first row of this launch (rows run on blockIdx.y)
+    int32_t row0;         // first row of this launch (row blocks run on blockIdx.y)
     const double *scale;  // coherency: per-row power-of-two scale (no unit normalisation), else nullptr
 };
 
@@ -141,6 +155,7 @@ struct TrialArgs {
     int64_t gstride;                   // bytes from one time point's planes to the next
     int64_t plane_bytes, cstride;
     int32_t chunk, tpad;
+    int32_t rows;                      // the planes' row count (npad)
 };
 
 // Coherency: per-row scale 2^-e with e the exponent of the row's largest
@@ -211,7 +226,8 @@ struct BwdPlanesArgs {      // W[s][k] = conj(u_k(s)): the product's B operand
     const void *z;           // complex rows of the window [n][ldz]
     int64_t ldz;
     int32_t n, tw, kpad;
-    uint8_t *w;              // planes [rows >= tw][kpad]
+    int32_t rows;            // row count of W's planes (>= tw, whole tiles)
+    uint8_t *w;              // planes, rows x kpad (stage-major, one block)
     int64_t plane_bytes;
 };
 
@@ -221,7 +237,8 @@ struct BwdMetricArgs {      // H = (Gbar + Gbar^H) / T: the product's A operand
     int32_t n, kpad;
     int32_t row0;            // first row of this launch (rows run on blockIdx.y)
     double inv_t;
-    uint8_t *h;              // planes [npad][kpad]
+    int32_t rows;            // row count of H's planes (npad)
+    uint8_t *h;              // planes, npad x kpad (stage-major, one block)
     int64_t plane_bytes;
 };
 

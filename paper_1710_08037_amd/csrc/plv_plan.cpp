@@ -365,7 +365,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         return PLV_OK;
     }
     for (GramPlan &g : plan.grams) {
-        // chunk-major blocks [nchunk][npad][chunk]
+        // nchunk blocks of npad x chunk phasors (stage-major inside)
         g.plane_bytes = align256((size_t)g.nchunk * g.npad * g.chunk * cb);
         g.u_off = off;
         off += g.plane_bytes * pl;
@@ -395,7 +395,6 @@ void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd)
         GramDesc d{};
         d.u = ws + g.u_off;
         d.plane_bytes = (int64_t)g.plane_bytes;
-        d.ldu = g.chunk;
         d.cstride = (int64_t)g.npad * g.chunk * cbytes_of(plan.mode);
         d.n = g.n;
         d.npad = g.npad;
@@ -414,7 +413,6 @@ void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd)
         d.ciplv = g.ciplv;
         d.g = g.g;
         if (plan.op == PLV_OP_BACKWARD_ANALYTIC || plan.op == PLV_OP_BACKWARD_REAL) {
-            d.ldu = g.kpad;
             d.cstride = 0;
             d.tpad = g.kpad;
             d.ub = ws + g.w_off;
