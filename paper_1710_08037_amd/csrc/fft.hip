@@ -420,42 +420,78 @@ __device__ inline void store_band(int mode, const GramDesc &g, const HilbertProb
     }
 }
 
-// Direct synthesis of a narrow band from the spectrum in LDS:
-// z(n) = (2/t) exp(2 pi i klo n / t) sum_{m < K} X_{klo+m} w^m, w = exp(2 pi i n / t),
-// four consecutive window samples per thread step so that each X_k read
-// serves four.  The root index klo n mod t is carried from step to step.
+// ------------------------------------------------------- band synthesis --
+// Direct synthesis of a narrow band from its bins X_k, klo <= k <= khi:
+// z(n) = (2/t) exp(2 pi i klo n / t) sum_{m < K} X_{klo+m} w^m, w = exp(2 pi i n / t)
+// (Horner in w).  One work-group takes SYNTH_S consecutive window samples of one
+// (problem, band) for SYNTH_R rows, 16 rows at a time: lane (quad q, row rr)
+// holds four samples of row rr, so a wave stores one contiguous stage-major
+// run of 16 rows.  The roots w and the base exp(2 pi i klo n / t) of a lane's
+// samples are loaded once and serve every row; the bins of the 16 rows pass
+// through LDS.
+// Work-groups of problem q: nbands x ceil(L / SYNTH_S) x ceil(n / SYNTH_R), L the
+// samples written per row (tpad for phasor planes, the window for the backward's
+// complex z); the host stores the running sums in a table of nprob + 1 entries.
 template <class R>
-__device__ inline void direct_band(int mode, const GramDesc &g, const HilbertProb &hp, int row, BandBins bb,
-                                   const cx<R> *buf)
+__global__ __launch_bounds__(256) void band_synth_kernel(HilbertArgs a, int mode)
 {
-    const int nt = blockDim.x, t = hp.t;
+    static_assert(SYNTH_S == 64 && SYNTH_R % 16 == 0, "16 quads of 4 samples, rows in groups of 16");
+    __shared__ cx<R> xs[16][DIRECT_KMAX];
+    // ---- which (problem, band, sample block, row chunk): scalar binary search
+    const int job = blockIdx.x;
+    int lo = 0, hi = a.nprob;  // prefix[lo] <= job < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.synth_prefix[mid] <= job)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int q = lo;
+    const HilbertProb hp = a.hp[q];
+    const GramDesc g0 = a.gd[hp.gram0];
+    const int len0 = g0.zbuf ? hp.tw : g0.tpad;  // samples synthesised per row (host counts the same)
+    const int nsb = (len0 + SYNTH_S - 1) / SYNTH_S;
+    int rest = job - a.synth_prefix[q];
+    const int b = rest % hp.nbands;
+    rest /= hp.nbands;
+    const int sb = rest % nsb, rc = rest / nsb;
+    const BandBins bb = a.bins[hp.bin0 + b];
+    if (!bb.direct)
+        return;
+    const GramDesc g = a.gd[hp.gram0 + b];
+    const int t = hp.t, klo = bb.klo, khi = bb.khi;
+    const int nk = khi >= klo ? khi - klo + 1 : 0;  // <= DIRECT_KMAX (host rule)
+    const int kl = nk ? klo : 0;
+    const int limit = g.zbuf ? hp.tw : g.tpad;
+    const int tid = threadIdx.x, qd = tid >> 4, rr = tid & 15;
+    const int s0 = sb * SYNTH_S + qd * 4;
     const cx<R> *roots = (const cx<R> *)hp.roots;
     const R scale = (R)2 / (R)t;
-    const int klo = bb.klo, khi = bb.khi;
-    const bool empty = klo > khi;
-    const int kl = empty ? 0 : klo;  // keeps the root index in range for an empty band
-    // root index of the thread's first sample and its advance per step
-    const int s_first = threadIdx.x * 4;
-    int idx = (int)(((int64_t)kl * (hp.t0 + s_first)) % t);
-    const int step = (int)(((int64_t)kl * 4 * nt) % t);
-    const int limit = g.zbuf ? hp.tw : g.tpad;
-    cx<R> *zrow = (cx<R> *)g.zbuf + (int64_t)row * g.ldz;
-    for (int s0 = s_first; s0 < limit; s0 += nt * 4) {
-        cx<R> w[4], acc[4], base[4];
-        int ix = idx;
+    cx<R> w[4], base[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int n = min(hp.t0 + s0 + v, t - 1);  // clamped: samples past the window are discarded
-            w[v] = gld(roots, n);
-            base[v] = gld(roots, ix);
-            acc[v] = cx<R>{0, 0};
-            ix += kl;
-            ix = ix >= t ? ix - t : ix;
+    for (int v = 0; v < 4; ++v) {
+        const int n = min(hp.t0 + s0 + v, t - 1);  // clamped: samples past the window are discarded
+        w[v] = gld(roots, n);
+        base[v] = gld(roots, (int)(((int64_t)kl * n) % t));
+    }
+    const cx<R> *xsrc = (const cx<R> *)hp.xbins + (int64_t)b * DIRECT_KMAX;
+    const int64_t xrow = (int64_t)hp.nbands * DIRECT_KMAX;  // bins of one row to the next
+    cx<R> *zrow0 = (cx<R> *)g.zbuf;
+    const int r_end = min(hp.n, (rc + 1) * SYNTH_R);
+    for (int r0 = rc * SYNTH_R; r0 < r_end; r0 += 16) {
+        __syncthreads();  // the previous group's bins are no longer read
+        for (int e = tid; e < 16 * nk; e += 256) {
+            const int r = r0 + e / nk, k = e % nk;
+            xs[e / nk][k] = r < hp.n ? gld(xsrc, r * xrow + k) : cx<R>{0, 0};
         }
-        idx += step;
-        idx = idx >= t ? idx - t : idx;
-        for (int k = khi; k >= klo; --k) {
-            const cx<R> xk = buf[lpad(k)];
+        __syncthreads();
+        const int row = r0 + rr;
+        if (row >= r_end || s0 >= limit)
+            continue;
+        cx<R> acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+        for (int k = nk - 1; k >= 0; --k) {
+            const cx<R> xk = xs[rr][k];
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 acc[v] = cadd(cmul(acc[v], w[v]), xk);
@@ -465,6 +501,7 @@ __device__ inline void direct_band(int mode, const GramDesc &g, const HilbertPro
         for (int v = 0; v < 4; ++v)
             z[v] = cscale(cmul(base[v], acc[v]), scale);  // 0 for an empty band
         if (g.zbuf) {
+            cx<R> *zrow = zrow0 + (int64_t)row * g.ldz;
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 if (s0 + v < hp.tw)
@@ -542,11 +579,14 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
             __syncthreads();
         }
 
-        // ---- narrow bands straight from the bins in buf
+        // ---- narrow bands: their bins to xbins, synthesised by band_synth_kernel
         for (int b = 0; b < hp.nbands; ++b) {
             const BandBins bb = a.bins[hp.bin0 + b];
-            if (bb.direct)
-                direct_band<R>(mode, a.gd[hp.gram0 + b], hp, rr.row, bb, buf);
+            if (bb.direct) {
+                cx<R> *dst = (cx<R> *)hp.xbins + ((int64_t)rr.row * hp.nbands + b) * DIRECT_KMAX;
+                for (int k = bb.klo + tid; k <= bb.khi; k += (int)blockDim.x)
+                    gst(dst, k - bb.klo, buf[lpad(k)]);
+            }
         }
         // ---- the other bands by inverse transform (each overwrites buf)
         for (int b = 0; b < hp.nbands; ++b) {
@@ -759,6 +799,19 @@ hipError_t launch_chirps(bool f64, int logm, const ChirpJob *jobs, int njobs, hi
     if (njobs <= 0)
         return hipSuccess;
     return dispatch_any(f64, logm, 0, 0, nullptr, jobs, njobs, 0, s);
+}
+
+hipError_t launch_band_synth(int mode, const HilbertArgs &a, int njobs, hipStream_t s)
+{
+    if (njobs <= 0)
+        return hipSuccess;
+    if (mode < M_F64 || mode > M_F16 || a.nprob <= 0 || !a.synth_prefix)
+        return hipErrorInvalidValue;
+    if (mode == M_F64)
+        band_synth_kernel<double><<<njobs, 256, 0, s>>>(a, mode);
+    else
+        band_synth_kernel<float><<<njobs, 256, 0, s>>>(a, mode);
+    return hipGetLastError();
 }
 
 hipError_t launch_hilbert(int mode, const HilbertArgs &a, int cus, hipStream_t s)

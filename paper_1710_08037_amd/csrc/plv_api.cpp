@@ -312,9 +312,11 @@ static BandBins band_bins(int t, double fs, const plv_band *band)
 // sample, twice for a Bluestein length.  The cheaper one is taken.
 static bool direct_band(const FftPlan &f, BandBins bb)
 {
-    if (bb.klo < 0)
+    if (bb.klo < 0 || !f.has_xbins)
         return false;  // plain analytic signal: every positive bin
     const int k = bb.khi >= bb.klo ? bb.khi - bb.klo + 1 : 0;
+    if (k > DIRECT_KMAX)
+        return false;  // more bins than a slot holds
     const double direct = 4.0 * k + 12.0;
     const double fft = (f.blue ? 2.0 : 1.0) * (double)(1 << f.logm) / (double)f.t * (2.5 * f.logm + 6.0);
     return direct < fft;
@@ -324,8 +326,13 @@ static bool direct_band(const FftPlan &f, BandBins bb)
 // grouped by FFT size (class_start / class_count per size), per-length jobs.
 static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const plv_grad *grads,
                             const plv_band *bands, int nbands, double fs, uint8_t *ws, std::vector<uint8_t> &blob,
-                            std::vector<int> &class_start, std::vector<int> &class_count)
+                            std::vector<int> &class_start, std::vector<int> &class_count, bool &any_direct,
+                            int64_t &synth_jobs)
 {
+    any_direct = false;
+    synth_jobs = 0;
+    const bool backward = plan.op == PLV_OP_BACKWARD_REAL;
+    int32_t *prefix = (int32_t *)(blob.data() + plan.synth_off);
     const size_t nprob = plan.fft.size();
     HilbertProb *hp = (HilbertProb *)(blob.data() + plan.hp_off);
     BandBins *bins = (BandBins *)(blob.data() + plan.bin_off);
@@ -352,14 +359,22 @@ static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const pl
         h.nbands = nbands;
         h.bin0 = (int32_t)(q * nbands);
         h.xbar = grads ? grads[q].din : nullptr;
+        h.xbins = f.has_xbins ? ws + f.xbin_off : nullptr;
         hp[q] = h;
         for (int b = 0; b < nbands; ++b) {
             BandBins bb = band_bins(f.t, fs, bands ? &bands[b] : nullptr);
             // (the adjoint kernel takes every band through the transform)
             bb.direct = direct_band(f, bb) ? 1 : 0;
+            any_direct = any_direct || bb.direct;
             bins[q * nbands + b] = bb;
         }
+        // band synthesis work-groups of this problem (band_synth_kernel's decode)
+        const GramPlan &g0 = plan.grams[q * nbands];
+        const int64_t len = backward ? g0.t : g0.tpad;
+        prefix[q] = (int32_t)synth_jobs;
+        synth_jobs += (int64_t)nbands * ((len + SYNTH_S - 1) / SYNTH_S) * ((p.n + SYNTH_R - 1) / SYNTH_R);
     }
+    prefix[nprob] = (int32_t)std::min<int64_t>(synth_jobs, INT32_MAX);
     size_t r = 0;
     for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
         class_start.push_back((int)r);
@@ -424,6 +439,8 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
         build_tables(plan, gd, items, tiles);
 
     std::vector<int> class_start, class_count;  // FFT rows per size class
+    bool any_direct = false;                    // some band synthesised from its bins
+    int64_t synth_jobs = 0;                     // its work-groups
     if (plan.grouped || real || plan.has_order) {
         std::vector<uint8_t> blob(plan.tables_bytes, 0);
         memcpy(blob.data() + plan.desc_off, gd.data(), gd.size() * sizeof(GramDesc));
@@ -440,7 +457,8 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             memcpy(blob.data() + plan.tile_off, tiles.data(), tiles.size() * sizeof(TileRef));
         }
         if (real)
-            fill_fft_tables(plan, probs, nullptr, bands, nbands, fs, ws, blob, class_start, class_count);
+            fill_fft_tables(plan, probs, nullptr, bands, nbands, fs, ws, blob, class_start, class_count, any_direct,
+                            synth_jobs);
         plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
         if (st != PLV_OK)
             return st;
@@ -464,6 +482,20 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             ha.nbands = nbands;
             if ((e = launch_hilbert(mode, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal kernel launch");
+            tm.launched();
+        }
+        if (any_direct) {
+            if (synth_jobs > INT32_MAX)
+                return fail(ctx, PLV_ERR_UNSUPPORTED, "band synthesis needs %lld work-groups", (long long)synth_jobs);
+            HilbertArgs ha{};
+            ha.hp = (const HilbertProb *)(ws + plan.hp_off);
+            ha.bins = (const BandBins *)(ws + plan.bin_off);
+            ha.gd = (const GramDesc *)(ws + plan.desc_off);
+            ha.nbands = nbands;
+            ha.nprob = (int32_t)plan.fft.size();
+            ha.synth_prefix = (const int32_t *)(ws + plan.synth_off);
+            if ((e = launch_band_synth(mode, ha, (int)synth_jobs, s)) != hipSuccess)
+                return hip_fail(ctx, e, "band synthesis kernel launch");
             tm.launched();
         }
     } else {
@@ -724,13 +756,16 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
         build_tables(plan, gd, items, tiles);
 
     std::vector<int> class_start, class_count;
+    bool any_direct = false;
+    int64_t synth_jobs = 0;
     {
         std::vector<uint8_t> blob(plan.tables_bytes, 0);
         memcpy(blob.data() + plan.desc_off, gd.data(), gd.size() * sizeof(GramDesc));
         if (plan.grouped)
             memcpy(blob.data() + plan.item_off, items.data(), items.size() * sizeof(Item));
         if (real)
-            fill_fft_tables(plan, probs, grads, bands, nbands, fs, ws, blob, class_start, class_count);
+            fill_fft_tables(plan, probs, grads, bands, nbands, fs, ws, blob, class_start, class_count, any_direct,
+                            synth_jobs);
         plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
         if (st != PLV_OK)
             return st;
@@ -754,6 +789,15 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
             ha.logm = plan.tw_logm[c];
             if ((e = launch_hilbert(mode, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal kernel launch");
+            ++nl;
+        }
+        if (any_direct) {
+            if (synth_jobs > INT32_MAX)
+                return fail(ctx, PLV_ERR_UNSUPPORTED, "band synthesis needs %lld work-groups", (long long)synth_jobs);
+            ha.nprob = (int32_t)plan.fft.size();
+            ha.synth_prefix = (const int32_t *)(ws + plan.synth_off);
+            if ((e = launch_band_synth(mode, ha, (int)synth_jobs, s)) != hipSuccess)
+                return hip_fail(ctx, e, "band synthesis kernel launch");
             ++nl;
         }
         tm.launched(nl);

@@ -185,7 +185,13 @@ struct HilbertProb {
     int32_t bin0;        // first entry of this problem in the band-bin table
     int32_t pad_;
     void *xbar;          // backward: dL/dx rows [n][ld] (same dtype as x)
+    void *xbins;         // bins of the directly synthesised bands: row r, band b at
+                         //   (r * nbands + b) * DIRECT_KMAX complex (nullptr: no band-pass bands)
 };
+
+// A band of at most DIRECT_KMAX bins may be synthesised directly from its
+// bins (by the band synthesis kernel) instead of by an inverse transform.
+constexpr int DIRECT_KMAX = 48;
 
 // Positive-frequency bins [klo, khi] that get weight 2; klo < 0 selects the
 // plain one-sided weights (1 at DC, 2 below Nyquist, 1 at Nyquist, 0 above).
@@ -207,7 +213,8 @@ struct HilbertArgs {
     int32_t logm;
     const GramDesc *gd;   // destinations of the phasor planes
     int32_t nbands;       // bands per problem (the same for every problem of a call)
-    int32_t pad_;
+    int32_t nprob;        // band synthesis: problems, and the running work-group counts
+    const int32_t *synth_prefix;  //   [nprob + 1] of the problems (see band_synth_kernel)
 };
 
 // Set-up for one distinct row length t: its root table, and for a Bluestein
@@ -277,6 +284,10 @@ hipError_t launch_chirps(bool f64, int logm, const ChirpJob *jobs, int njobs, hi
 // kernel's occupancy
 hipError_t launch_hilbert(int mode, const HilbertArgs &a, int cus, hipStream_t s);
 hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int cus, hipStream_t s);
+// after launch_hilbert: the bands with BandBins::direct of every problem, from
+// their bins in HilbertProb::xbins; njobs = a.synth_prefix[a.nprob] work-groups
+hipError_t launch_band_synth(int mode, const HilbertArgs &a, int njobs, hipStream_t s);
+constexpr int SYNTH_S = 64, SYNTH_R = 64;  // samples and rows per band-synthesis work-group
 hipError_t launch_planes_t(int mode, const BwdPlanesArgs &a, hipStream_t s);
 hipError_t launch_metric_adjoint(int mode, const BwdMetricArgs &a, hipStream_t s);
 hipError_t launch_normalise_adjoint(bool f64, const BwdNormArgs &a, hipStream_t s);

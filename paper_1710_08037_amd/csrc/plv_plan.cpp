@@ -326,6 +326,8 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         off += align256(plan.nrows * sizeof(RowRef));
         plan.job_off = off;
         off += align256(plan.lens.size() * sizeof(ChirpJob));
+        plan.synth_off = off;
+        off += align256((size_t)(nprob + 1) * sizeof(int32_t));
         plan.tables_bytes = off;
         for (int lg : plan.tw_logm) {
             plan.tw_off.push_back(off);
@@ -339,6 +341,20 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
                 off += align256((size_t)l.t * csz);
                 l.bhat_off = off;
                 off += align256((size_t)(1 << l.logm) * csz);
+            }
+        }
+        // band-pass bands may be synthesised from their bins: a slot of
+        // DIRECT_KMAX bins per row and band (fs, and so the bin counts, are
+        // only known at the call)
+        bool bandpass = false;
+        for (int b = 0; bands && b < nbands; ++b)
+            bandpass = bandpass || bands[b].f_lo != 0.0 || bands[b].f_hi != 0.0;
+        if (bandpass) {
+            for (int64_t q = 0; q < nprob; ++q) {
+                FftPlan &f = plan.fft[q];
+                f.has_xbins = true;
+                f.xbin_off = off;
+                off += align256((size_t)probs[q].n * nbands * DIRECT_KMAX * csz);
             }
         }
     } else {

@@ -40,6 +40,8 @@ struct FftPlan {
     bool blue = false;
     int tw_index = 0;     // which twiddle table (by logm)
     int len_index = 0;    // which per-length set-up (by t)
+    size_t xbin_off = 0;  // bins of directly synthesised bands (only with band-pass bands)
+    bool has_xbins = false;
 };
 
 // Set-up tables of one distinct row length.
@@ -66,6 +68,7 @@ struct Plan {
     std::vector<size_t> tw_off;
     std::vector<LenPlan> lens;                // distinct row lengths, ordered by (logm, t)
     size_t hp_off = 0, bin_off = 0, row_off = 0, job_off = 0;
+    size_t synth_off = 0;  // band synthesis: running work-group counts [nprob + 1]
     size_t nrows = 0;
     size_t total = 0;
 };
