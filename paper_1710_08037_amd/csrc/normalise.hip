@@ -1,10 +1,11 @@
 // normalise.hip -- analytic signal -> unit phasors (Section II.A, Eq. 4), and
 // for coherency (Section II.B, Eq. 12) the rows scaled by a power of two.
 //
-// u = z / |z| replaces the angle() + exp() of the per-pair formulation.  |z| is
-// formed from components rescaled by an exact power of two, so FP32 neither
-// underflows nor overflows for any finite z.  z = 0 (either zero sign) maps to
-// 1 + 0i, the phasor of angle(0) = 0.  The result is written in the Gram
+// u = z / |z| replaces the angle() + exp() of the per-pair formulation.  For
+// components of ordinary size 1/|z| is one hardware reciprocal square root;
+// otherwise |z| is formed from components rescaled by an exact power of two,
+// so FP32 neither underflows nor overflows for any finite z (phasor.h).  z = 0
+// (either zero sign) maps to 1 + 0i, the phasor of angle(0) = 0.  The result is written in the Gram
 // kernel's operand format: interleaved (re, im) per sample, as bf16 / f16 / f32
 // / f64, or as two bf16 planes hi = rn(u), lo = rn(u - hi) for the split mode.
 // Samples past the window are written as 0 + 0i up to the padded length.

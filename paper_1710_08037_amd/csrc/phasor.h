@@ -10,17 +10,25 @@ namespace plv {
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
-// u = z / |z|, with |z| formed from components rescaled by an exact power of
-// two (no under/overflow for any finite z); z = 0 (either zero sign) -> 1 + 0i,
-// the phasor of angle(0) = 0.  NaN/Inf propagate as NaN.
+// u = z / |z|.  When the larger component lies in [2^-60, 2^60], re^2 + im^2
+// is a normal FP32 number and one hardware reciprocal square root (about 1
+// ulp) gives 1/|z|.  Otherwise |z| is formed from components rescaled by an
+// exact power of two (no under/overflow for any finite z); z = 0 (either zero
+// sign) -> 1 + 0i, the phasor of angle(0) = 0.  NaN/Inf propagate as NaN.
 __device__ inline void unit_phasor(float re, float im, float &ur, float &ui)
 {
+    float m = fmaxf(fabsf(re), fabsf(im));
+    if (m >= 0x1p-60f && m <= 0x1p60f) {
+        const float inv = __builtin_amdgcn_rsqf(fmaf(re, re, im * im));
+        ur = re * inv;
+        ui = im * inv;
+        return;
+    }
     if (re == 0.0f && im == 0.0f) {
         ur = 1.0f;
         ui = 0.0f;
         return;
     }
-    float m = fmaxf(fabsf(re), fabsf(im));
     int e;
     (void)frexpf(m, &e);
     float a = ldexpf(re, -e), b = ldexpf(im, -e);  // exact rescale, max(|a|,|b|) in [0.5, 1)

@@ -287,7 +287,7 @@ hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int cus, hipSt
 // after launch_hilbert: the bands with BandBins::direct of every problem, from
 // their bins in HilbertProb::xbins; njobs = a.synth_prefix[a.nprob] work-groups
 hipError_t launch_band_synth(int mode, const HilbertArgs &a, int njobs, hipStream_t s);
-constexpr int SYNTH_S = 64, SYNTH_R = 64;  // samples and rows per band-synthesis work-group
+constexpr int SYNTH_S = 64, SYNTH_R = 256;  // samples and rows per band-synthesis work-group
 hipError_t launch_planes_t(int mode, const BwdPlanesArgs &a, hipStream_t s);
 hipError_t launch_metric_adjoint(int mode, const BwdMetricArgs &a, hipStream_t s);
 hipError_t launch_normalise_adjoint(bool f64, const BwdNormArgs &a, hipStream_t s);
