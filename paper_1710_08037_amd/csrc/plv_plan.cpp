@@ -18,38 +18,45 @@ std::string msg(const char *fmt, long long a = 0, long long b = 0)
 }
 
 // K-chunks of a problem computed alone.  Every (tile, chunk) item costs about
-// the same, so the launch takes ceil(items / slots) rounds of work-groups; the
-// chunk count is the one that fills those rounds best (fewest chunks among
-// equals), with no chunk longer than the mode's maximum and none shorter than MIN_CHUNK
-// unless T itself is.  Partial slots are capped by PARTIAL_BUDGET; beyond it
-// the chunks run in passes.
+// the same, so a pass takes ceil(items / slots) rounds of work-groups; the
+// chunk count is the one with the least estimated time (below), with no chunk
+// longer than the mode's maximum and none shorter than MIN_CHUNK unless T
+// itself is.  Partial slots are capped by PARTIAL_BUDGET; beyond it the chunks
+// run in passes.
+constexpr double ITEM_OVERHEAD = 512.0;  // fixed cost of a work item, in samples of K
+
 void choose_chunks_single(GramPlan &g, int slots, int bm, int maxc)
 {
+    // Estimated time of a chunk count: for each pass, the rounds of work-groups
+    // the GPU runs (items / slots, rounded up) times the length of one item,
+    // its chunk plus a fixed per-item cost (prologue, fold, partial store) in
+    // samples.  Ties go to fewer chunks: fewer partial slots to write and sum.
     const int kgr = g.tpad / PLV_KGRAN;
     const int lo = std::max(1, (g.tpad + maxc - 1) / maxc);
     const int hi = std::max(lo, std::min(kgr, std::max(1, g.tpad / MIN_CHUNK)));
+    const size_t slot_bytes = (size_t)g.nupper * 2 * bm * bm * sizeof(double);
+    const int budget = (int)std::max<size_t>(1, std::min<size_t>(INT32_MAX, PARTIAL_BUDGET / slot_bytes));
     int best = lo;
-    double best_eff = -1.0;
+    double best_cost = -1.0;
     for (int nc = lo; nc <= hi && nc <= lo + 4 * slots; ++nc) {
         const int per = (kgr + nc - 1) / nc;
         const int real_nc = (kgr + per - 1) / per;
         if (real_nc != nc)
             continue;
-        const double items = (double)g.nupper * nc;
-        const double rounds = std::ceil(items / slots);
-        const double eff = items / (rounds * slots);
-        if (eff > best_eff + 1e-9) {
-            best_eff = eff;
+        const int nslot = std::min(nc, budget);
+        double rounds = 0.0;
+        for (int c0 = 0; c0 < nc; c0 += nslot)
+            rounds += std::ceil((double)g.nupper * std::min(nslot, nc - c0) / slots);
+        const double cost = rounds * ((double)per * PLV_KGRAN + ITEM_OVERHEAD);
+        if (best_cost < 0.0 || cost < best_cost * (1.0 - 1e-9)) {
+            best_cost = cost;
             best = nc;
         }
-        if (eff > 0.97)
-            break;  // good enough: prefer fewer, longer chunks
     }
     const int per = (kgr + best - 1) / best;  // granules per chunk
     g.chunk = per * PLV_KGRAN;
     g.nchunk = (kgr + per - 1) / per;
-    const size_t slot_bytes = (size_t)g.nupper * 2 * bm * bm * sizeof(double);
-    g.nslot = (int)std::max<size_t>(1, std::min<size_t>(g.nchunk, PARTIAL_BUDGET / slot_bytes));
+    g.nslot = std::min(g.nchunk, budget);
 }
 
 // Inside a grouped launch every chunk of a problem has its own slot (one pass).
@@ -70,7 +77,6 @@ void choose_chunks_grouped(GramPlan &g, int maxc)
 // ids (XCD x = id mod 8 runs entries x * len .. x * len + len - 1 in order).
 // A plain longest-first order of items would hand XCD 0 all the longest ones.
 constexpr int NXCD = 8;
-constexpr double ITEM_OVERHEAD = 512.0;  // fixed cost of an item, in samples of K
 
 void schedule_items(Plan &plan)
 {
