@@ -110,6 +110,33 @@ def test_grouped_uneven_problems_with_bands(prec):
             compare(to_np(outs[k], b), ref, TOL[prec], "problem %d band %d" % (k, b))
 
 
+@pytest.mark.parametrize("prec", ["f32", "split_bf16"])
+def test_band_bin_cap_and_row_chunks(prec):
+    """N = 600 rows (the band synthesis takes rows in chunks of 256: two full
+    chunks and a ragged one) of T = 2049 samples (Bluestein, M = 8192, where
+    the cost rule prefers direct synthesis up to ~74 bins): a band of exactly
+    48 bins (the most a bin slot holds: direct), one of 49 (inverse
+    transform), a 4 Hz band and an empty band (no bin: z = 0, unit phasor
+    1).  Checked on all pairs among rows at the chunk edges and random rows."""
+    n, t, fs = 600, 2049, 1000.0
+    hz = fs / t
+    bands = [(99.5 * hz, 147.5 * hz), (99.5 * hz, 148.5 * hz), (8.0, 12.0), (0.1 * hz, 0.2 * hz)]
+    x = synth.glag_real(n, t, fs, 6, (8, 70), seed=611)
+    out = plv_mod().from_real(real_dev(x, prec), fs, bands=bands, prec=prec, want_g=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(612)
+    edge = [0, 1, 254, 255, 256, 257, 510, 511, 512, 513, 598, 599]
+    rows = np.unique(np.concatenate([edge, rng.choice(n, size=8, replace=False)]))
+    xr = exact_real(x[rows], prec)
+    for b, band in enumerate(bands):
+        got = {k: v[np.ix_(rows, rows)] for k, v in to_np(out, b).items()}
+        ref = oracle.full_from_real(xr, fs, band)
+        compare(got, ref, TOL[prec], "band %d %s" % (b, prec))
+    # the empty band: every phasor is 1, so every PLV is 1 and every iPLV 0
+    e = to_np(out, 3)
+    assert np.all(e["plv"] == 1.0) and np.all(e["iplv"] == 0.0)
+
+
 @pytest.mark.parametrize("prec", ["split_bf16", "f32"])
 def test_differentiable_case_size_sampled_rows(prec):
     """N = 2048 real signals of T = 8192 samples at 1 kHz, 32 latents: the
