@@ -110,6 +110,21 @@ def test_grouped_uneven_problems_with_bands(prec):
             compare(to_np(outs[k], b), ref, TOL[prec], "problem %d band %d" % (k, b))
 
 
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_bands_in_16_bit_modes(prec):
+    """The 16-bit plane formats through both band paths: narrow bands from
+    their bins (band synthesis kernel) and a wide band by inverse transform,
+    N = 40 rows of T = 1500 (Bluestein) at 1 kHz."""
+    n, t, fs = 40, 1500, 1000.0
+    bands = [(8.0, 12.0), (18.0, 22.0), (5.0, 200.0)]
+    x = synth.glag_real(n, t, fs, 4, (8, 22), seed=613)
+    out = plv_mod().from_real(real_dev(x, prec), fs, bands=bands, prec=prec, want_g=True)
+    torch.cuda.synchronize()
+    xr = exact_real(x, prec)
+    for b, band in enumerate(bands):
+        compare(to_np(out, b), oracle.full_from_real(xr, fs, band), TOL[prec], "band %s %s" % (band, prec))
+
+
 @pytest.mark.parametrize("prec", ["f32", "split_bf16"])
 def test_band_bin_cap_and_row_chunks(prec):
     """N = 600 rows (the band synthesis takes rows in chunks of 256: two full
