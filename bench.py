@@ -127,7 +127,8 @@ def cpu_baseline(z_np, gpu_out, budget_s=15.0):
         dt = time.perf_counter() - t0
         return g, pr, dt
 
-    g, pr, dt = run(32)
+    # calibrate on enough rows that the threaded oracle runs at its full rate
+    g, pr, dt = run(min(z_np.shape[0], 96))
     rate = len(pr) * t / dt
     want_pairs = rate * budget_s / t
     r = int(min(z_np.shape[0], max(32, math.sqrt(2 * want_pairs))))
