@@ -94,17 +94,28 @@ def measured_traffic(kernel, workload):
     return None
 
 
+def issued_flops(prec, n, t):
+    """MFMA work the Gram kernel issues: whole BM x BM tiles of the upper
+    triangle (diagonal tiles in full, rows padded to the tile) over K padded
+    to 32 samples."""
+    bm = 64 if prec == "f64" else 128
+    ntile = -(-n // bm)
+    return FLOP_PER_PAIR_SAMPLE[prec] * (ntile * (ntile + 1) // 2) * bm * bm * (-(-t // 32) * 32)
+
+
 def roofline(prec, n, t, stages):
     ms, calls, launches = stages["gram"]
     per_launch_s = ms / max(launches, 1) / 1e3
     flops = FLOP_PER_PAIR_SAMPLE[prec] * (n * (n - 1) // 2) * t
     achieved = flops / per_launch_s / 1e12
     peak = PEAK_TFLOPS[prec]
+    issued_tf = issued_flops(prec, n, t) / per_launch_s / 1e12
     return {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
             "traffic": measured_traffic("herk_kernel<%s>" % prec, "n%d_t%d" % (n, t)),
             "kernel": "herk_kernel<%s>" % prec, "kernel_ms": round(per_launch_s * 1e3, 4),
-            "flop_per_pair_sample": FLOP_PER_PAIR_SAMPLE[prec]}
+            "flop_per_pair_sample": FLOP_PER_PAIR_SAMPLE[prec],
+            "issued_achieved": round(issued_tf, 2), "issued_frac": round(issued_tf / peak, 4)}
 
 
 def cpu_baseline(z_np, gpu_out, budget_s=15.0):
@@ -259,6 +270,8 @@ def bench_coherence(args):
     if stages.get("gram"):
         flops = FLOP_PER_PAIR_SAMPLE[prec] * ps
         extra["gram_frac_of_peak"] = round(flops / (stages["gram"] / 1e3) / 1e12 / PEAK_TFLOPS[prec], 4)
+        extra["gram_issued_frac_of_peak"] = round(issued_flops(prec, n, t) / (stages["gram"] / 1e3) / 1e12
+                                                  / PEAK_TFLOPS[prec], 4)
     return line_for("coherency: N=1024 complex coefficient rows x T=60000, amplitude-modulated mixtures",
                     ps / (ms / 1e3), ms, args, "bf16", {"n": n, "t": t, "prec": prec}, extra)
 
@@ -313,6 +326,8 @@ def bench_brain(args):
         flops = FLOP_PER_PAIR_SAMPLE[prec] * ps
         extra["gram_tflops"] = round(flops / (stages["gram"] / 1e3) / 1e12, 1)
         extra["gram_frac_of_peak"] = round(flops / (stages["gram"] / 1e3) / 1e12 / PEAK_TFLOPS[prec], 4)
+        extra["gram_issued_frac_of_peak"] = round(issued_flops(prec, n, t) / (stages["gram"] / 1e3) / 1e12
+                                                  / PEAK_TFLOPS[prec], 4)
     if not args.no_cpu:
         extra["cpu_baseline"], extra["max_abs_err"] = brain_cpu_leg(z, pairs, box["out"])
     extra["steps_note"] = "at most 3 timed steps of about a second each"
