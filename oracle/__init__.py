@@ -10,7 +10,10 @@ What is computed, and where it comes from in the paper (Bruna, Maestu, Pereda,
 "Phase Locking Value revisited"):
 
 * ``analytic``      Eq. 3: the (band-pass) analytic signal, as the DFT-domain
-                    construction with one-sided weights, by plain DFT sums.
+                    construction with one-sided weights, by plain DFT sums; the
+                    band-pass a DFT-bin mask or a forward-backward FIR
+                    (``fir_taps``, ``fir_power``: the build's own design, since
+                    the paper names an FIR without giving it).
 * ``phase``         Eq. 3 / Appendix, first listing: angle of z (0 at z = 0).
 * ``pair_means``    Eq. 2 per pair, the original formulation: the mean over
                     samples of exp(i * phase difference).
@@ -70,6 +73,12 @@ def lib():
             L = C.CDLL(_SO)
             L.oracle_mask_plain.argtypes = [C.c_int64, _D]
             L.oracle_mask_band.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, _D]
+            L.oracle_fir_taps.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, _D]
+            L.oracle_fir_taps.restype = C.c_int
+            L.oracle_fir_power.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int64, _D]
+            L.oracle_fir_power.restype = C.c_int
+            L.oracle_mask_fir.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_double, C.c_int64, _D]
+            L.oracle_mask_fir.restype = C.c_int
             L.oracle_spectral_filter.argtypes = [_D, _D, C.c_int64, C.c_int64, C.c_int64, _D, _D, _D,
                                                  C.c_int64, C.c_int]
             L.oracle_spectral_filter.restype = C.c_int
@@ -119,6 +128,47 @@ def mask_band(t: int, fs: float, flo: float, fhi: float) -> np.ndarray:
     return h
 
 
+def fir_taps(order: int, fs: float, flo: float, fhi: float) -> np.ndarray:
+    """Taps of the band-pass FIR (even order L, L + 1 taps): windowed ideal
+    band-pass, Hamming window, unit gain at the band centre."""
+    h = np.empty(int(order) + 1, dtype=np.float64)
+    if lib().oracle_fir_taps(int(order), float(fs), float(flo), float(fhi), _p(h)):
+        raise ValueError("FIR order must be even and positive")
+    return h
+
+
+def fir_power(t: int, fs: float, flo: float, fhi: float, order: int) -> np.ndarray:
+    """|H|^2 on the T-point DFT grid: the gain of forward-backward filtering."""
+    p = np.empty(int(t), dtype=np.float64)
+    if lib().oracle_fir_power(int(t), float(fs), float(flo), float(fhi), int(order), _p(p)):
+        raise ValueError("FIR order must be even and positive")
+    return p
+
+
+def mask_fir(t: int, fs: float, flo: float, fhi: float, order: int) -> np.ndarray:
+    h = np.empty(int(t), dtype=np.float64)
+    if lib().oracle_mask_fir(int(t), float(fs), float(flo), float(fhi), int(order), _p(h)):
+        raise ValueError("FIR order must be even and positive")
+    return h
+
+
+def mask(t: int, fs: float | None, band) -> np.ndarray:
+    """Spectrum weights of the analytic signal: plain (band None), a DFT-bin
+    band (flo, fhi), or a forward-backward FIR band (flo, fhi, order)."""
+    if band is None:
+        return mask_plain(t)
+    if len(band) > 2 and band[2]:
+        return mask_fir(t, fs, band[0], band[1], int(band[2]))
+    return mask_band(t, fs, band[0], band[1])
+
+
+def fir_zero_phase(x: np.ndarray, fs: float, band) -> np.ndarray:
+    """The real rows after forward-backward FIR filtering, as the DFT-domain
+    product with |H|^2 (circular over the row)."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    return spectral_filter(x, fir_power(x.shape[1], fs, band[0], band[1], int(band[2]))).real
+
+
 def spectral_filter(x: np.ndarray, h: np.ndarray, nthreads: int | None = None) -> np.ndarray:
     """IDFT(h .* DFT(x)) for every row of x (real or complex), by plain DFT sums."""
     x = np.atleast_2d(x)
@@ -141,11 +191,12 @@ def spectral_filter(x: np.ndarray, h: np.ndarray, nthreads: int | None = None) -
 
 
 def analytic(x: np.ndarray, fs: float | None = None, band=None, nthreads=None) -> np.ndarray:
-    """Analytic signal of each real row: plain one-sided weights, or the
-    band-pass weights of ``band = (flo, fhi)`` in Hz (needs ``fs``)."""
+    """Analytic signal of each real row: plain one-sided weights, the
+    band-pass weights of ``band = (flo, fhi)`` in Hz (needs ``fs``), or the
+    forward-backward FIR of ``band = (flo, fhi, order)``."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     t = x.shape[1]
-    h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
+    h = mask(t, fs, band)
     return spectral_filter(x, h, nthreads)
 
 
@@ -155,7 +206,7 @@ def analytic_fft(x: np.ndarray, fs: float | None = None, band=None) -> np.ndarra
     long or too many for O(T^2) sums."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     t = x.shape[1]
-    h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
+    h = mask(t, fs, band)
     return np.fft.ifft(h * np.fft.fft(x, axis=-1), axis=-1)
 
 
@@ -366,7 +417,7 @@ def grad_from_real(x: np.ndarray, fs=None, band=None, gp=None, gi=None, gc=None,
     """
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     t = x.shape[1]
-    h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
+    h = mask(t, fs, band)
     z = spectral_filter(x, h, nthreads)
     zbar = grad_from_analytic(z, gp, gi, gc, window, nthreads)
     return spectral_filter(zbar, h, nthreads).real
@@ -413,5 +464,5 @@ def grad_from_real_rows(x: np.ndarray, rows, fs=None, band=None, gp=None, gi=Non
     lib().oracle_phase_to_z(_p(zr), _p(zi), _p(dphi), zr.size, _p(dzr), _p(dzi))
     zbar = np.zeros((len(rows), t), dtype=np.complex128)
     zbar[:, w0:w1] = dzr + 1j * dzi
-    h = mask_plain(t) if band is None else mask_band(t, fs, band[0], band[1])
+    h = mask(t, fs, band)
     return spectral_filter(zbar, h, nthreads).real

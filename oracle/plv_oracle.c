@@ -8,7 +8,8 @@
  * What it follows (Bruna, Maestu, Pereda, "Phase Locking Value revisited"):
  *   - analytic signal (Section II.A, Eq. 3): z = x_BP + i*Hilbert{x_BP}, built
  *     here as the DFT-domain construction (one-sided spectrum weights h_k) with
- *     plain O(T^2) DFT sums, no FFT;
+ *     plain O(T^2) DFT sums, no FFT; the band-pass x_BP either a DFT-bin mask
+ *     or a forward-backward FIR (Section III names one, without its design);
  *   - instantaneous phase (Eq. 3 and the Appendix's first listing): the angle
  *     of z, atan2(Im z, Re z); an exact zero z gets phase 0;
  *   - PLV over time (Section II.A, Eq. 2): for each pair, the mean over t of
@@ -67,6 +68,76 @@ void oracle_mask_band(int64_t t, double fs, double flo, double fhi, double *h)
         int positive = (k > 0) && (2 * k < t);
         h[k] = (positive && f >= flo && f <= fhi) ? 2.0 : 0.0;
     }
+}
+
+/* FIR band-pass applied forward and backward (the paper's filtering before
+ * the Hilbert transform, Section III; its design is not given there, so this
+ * is the build's own definition).  Taps: the ideal band-pass impulse response
+ * between flo and fhi (Hz, sampling rate fs) sampled at n = m - L/2,
+ * m = 0..L (L even, L + 1 taps), times the symmetric Hamming window
+ * 0.54 - 0.46 cos(2 pi m / L), then scaled to unit gain at the band centre
+ * (flo + fhi) / 2.  Returns 0, or -1 for an odd or non-positive order. */
+int oracle_fir_taps(int64_t order, double fs, double flo, double fhi, double *taps)
+{
+    if (order <= 0 || (order & 1))
+        return -1;
+    const double a = flo / fs, b = fhi / fs;  /* cycles per sample */
+    const double half = (double)(order / 2);
+    for (int64_t m = 0; m <= order; ++m) {
+        const double n = (double)m - half;
+        const double ideal = (m == order / 2) ? 2.0 * (b - a)
+                                              : (sin(2.0 * M_PI * b * n) - sin(2.0 * M_PI * a * n)) / (M_PI * n);
+        const double w = 0.54 - 0.46 * cos(2.0 * M_PI * (double)m / (double)order);
+        taps[m] = ideal * w;
+    }
+    /* gain at the centre frequency: the taps are symmetric about L/2 */
+    const double fc = 0.5 * (a + b);
+    double g = 0.0;
+    for (int64_t m = 0; m <= order; ++m)
+        g += taps[m] * cos(2.0 * M_PI * fc * ((double)m - half));
+    for (int64_t m = 0; m <= order; ++m)
+        taps[m] /= g;
+    return 0;
+}
+
+/* Zero-phase gain of that filter on the T-point DFT grid: forward then
+ * backward filtering multiplies bin k by |H(exp(2 pi i k / T))|^2, with
+ * H(e^{iw}) = sum_m taps[m] e^{-i w m} summed directly (angle index k m mod T).
+ * Returns 0, or -1 for a bad order or an allocation failure. */
+int oracle_fir_power(int64_t t, double fs, double flo, double fhi, int64_t order, double *p)
+{
+    double *taps = (double *)malloc(sizeof(double) * (size_t)(order + 1));
+    if (!taps || oracle_fir_taps(order, fs, flo, fhi, taps)) {
+        free(taps);
+        return -1;
+    }
+    for (int64_t k = 0; k < t; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int64_t m = 0; m <= order; ++m) {
+            const double ang = 2.0 * M_PI * (double)((k * m) % t) / (double)t;
+            re += taps[m] * cos(ang);
+            im -= taps[m] * sin(ang);
+        }
+        p[k] = re * re + im * im;
+    }
+    free(taps);
+    return 0;
+}
+
+/* Analytic signal of the FIR-filtered row: the one-sided weights above times
+ * the zero-phase gain.  Returns 0 or -1 as oracle_fir_power. */
+int oracle_mask_fir(int64_t t, double fs, double flo, double fhi, int64_t order, double *h)
+{
+    double *p = (double *)malloc(sizeof(double) * (size_t)t);
+    if (!p || oracle_fir_power(t, fs, flo, fhi, order, p)) {
+        free(p);
+        return -1;
+    }
+    oracle_mask_plain(t, h);
+    for (int64_t k = 0; k < t; ++k)
+        h[k] *= p[k];
+    free(p);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
