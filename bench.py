@@ -252,6 +252,32 @@ def bench_grad(args):
                     args, "bf16", {"n": n, "t": t, "prec": args.prec_batch}, {"stage_ms": stages})
 
 
+def bench_fir(args):
+    import numpy as np
+    import torch
+
+    import paper_1710_08037_amd as plv
+    import synth
+
+    n, t, fs, order, pad = 2048, 8192, 1000.0, 2000, 2048
+    x = torch.from_numpy(synth.glag_real(n, t, fs, 32, (8.0, 12.0), seed=synth.seed_for(7),
+                                         dtype=np.float32)).cuda()
+    prec = args.prec_batch
+    bands = [(8.0, 12.0, order)]
+    win = (pad, t - pad)
+    ms, stages = timed(lambda: plv.from_real(x, fs, bands=bands, prec=prec, window=win), args.steps, args.warmup)
+    tw = win[1] - win[0]
+    ps = n * (n - 1) // 2 * tw
+    extra = {"stage_ms": stages}
+    if stages.get("gram"):
+        flops = FLOP_PER_PAIR_SAMPLE[prec] * ps
+        extra["gram_frac_of_peak"] = round(flops / (stages["gram"] / 1e3) / 1e12 / PEAK_TFLOPS[prec], 4)
+    return line_for("FIR band-pass then PLV: N=2048 real f32 x T=8192 at 1 kHz (4096-sample epoch, 2048 "
+                    "samples of padding each side), 8-12 Hz FIR of order 2000 applied forward and backward",
+                    ps / (ms / 1e3), ms, args, "bf16", {"n": n, "t": t, "window": list(win), "fir_order": order,
+                                                       "prec": prec}, extra)
+
+
 def bench_coherence(args):
     """Coherency (Section II.B, Eq. 12) of N = 1024 complex rows x T = 60000
     samples (amplitude-modulated coupled coefficients, complex64)."""
@@ -400,7 +426,7 @@ def main():
                     help="paths to time (both: split-BF16 for `value`, FP32 beside it)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 3 times (counter calibration) and exit")
-    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain", "coherence", "trials"])
+    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain", "coherence", "trials", "fir"])
     ap.add_argument("--prec-batch", default="split_bf16", help="precision of the batch and grad workloads")
     ap.add_argument("--prec-brain", default="bf16", choices=["bf16", "f16"], help="precision of the brain workload")
     args = ap.parse_args()
@@ -423,7 +449,7 @@ def main():
         print(json.dumps({"copy_ref_bytes": args.copy_ref}), flush=True)
         return
     if args.workload != "sensor":
-        fn = {"small": bench_small, "batch": bench_batch, "grad": bench_grad, "brain": bench_brain,
+        fn = {"small": bench_small, "batch": bench_batch, "grad": bench_grad, "brain": bench_brain, "fir": bench_fir,
               "coherence": bench_coherence, "trials": bench_trials}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return

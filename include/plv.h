@@ -108,13 +108,28 @@ typedef struct {
                        for PLV_PREC_F64), or NULL.  Needed later by plv_backward.     */
 } plv_problem;
 
-/* Band of the analytic signal for real input, in Hz, both edges included:
- * weight 2 on the positive-frequency DFT bins k with f_lo <= k*fs/T <= f_hi
- * (T = the full length t of the row), 0 on every other bin including DC and
- * Nyquist.  f_lo = f_hi = 0 selects the plain analytic signal (weights 1 at DC,
- * 2 below Nyquist, 1 at Nyquist for even T, 0 above). */
+/* Band of the analytic signal for real input, in Hz (Section II.A, Eq. 3).
+ * fir_order = 0: a DFT-bin band, both edges included: weight 2 on the
+ *   positive-frequency DFT bins k with f_lo <= k*fs/T <= f_hi (T = the full
+ *   length t of the row), 0 on every other bin including DC and Nyquist.
+ *   f_lo = f_hi = 0 selects the plain analytic signal (weights 1 at DC, 2 below
+ *   Nyquist, 1 at Nyquist for even T, 0 above).
+ * fir_order = L > 0 (even, <= PLV_FIR_MAX_ORDER, f_lo < f_hi <= fs/2): the
+ *   forward-backward FIR band-pass the paper applies before the Hilbert
+ *   transform (Section III; its design is not given there).  Taps: the ideal
+ *   band-pass between f_lo and f_hi sampled at n = m - L/2, m = 0..L, times the
+ *   Hamming window 0.54 - 0.46 cos(2 pi m / L), scaled to unit gain at
+ *   (f_lo + f_hi) / 2.  Applied as the zero-phase gain |H|^2 on the row's DFT
+ *   bins together with the plain one-sided weights, i.e. a circular
+ *   convolution over the row with the taps and their reverse: it equals
+ *   filtering forward then backward on every sample at least L from both ends
+ *   of the row, so rows should carry at least L samples of real padding on
+ *   each side, trimmed by [t0, t1). */
+#define PLV_FIR_MAX_ORDER 16384
 typedef struct {
     double f_lo, f_hi;
+    int32_t fir_order; /* 0: DFT-bin band; L > 0: FIR band-pass of order L */
+    int32_t reserved;  /* 0 */
 } plv_band;
 
 /* Upstream gradients for plv_backward: dL/d(output) as full [nbands][n][n]

@@ -29,7 +29,7 @@ class Trials(C.Structure):
 
 
 class Band(C.Structure):
-    _fields_ = [("f_lo", C.c_double), ("f_hi", C.c_double)]
+    _fields_ = [("f_lo", C.c_double), ("f_hi", C.c_double), ("fir_order", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Grad(C.Structure):
@@ -128,6 +128,8 @@ def bands(pairs):
     if pairs is None:
         return None, 1
     arr = (Band * len(pairs))()
-    for k, (lo, hi) in enumerate(pairs):
-        arr[k] = Band(float(lo), float(hi))
+    for k, band in enumerate(pairs):
+        lo, hi = band[0], band[1]
+        order = int(band[2]) if len(band) > 2 and band[2] else 0
+        arr[k] = Band(float(lo), float(hi), order, 0)
     return arr, len(pairs)

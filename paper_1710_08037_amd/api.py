@@ -190,7 +190,9 @@ def from_real_batch(xs, fs, bands=None, prec="split_bf16", windows=None, want=AL
     """PLV/iPLV/ciPLV of real signals, the analytic signal formed on the GPU.
 
     xs: list of real GPU tensors [n_k, t_k] (float32; float64 for f64).
-    bands: list of (f_lo, f_hi) in Hz or None for the plain analytic signal.
+    bands: list of (f_lo, f_hi) in Hz (a DFT-bin band), (f_lo, f_hi, order) (the
+    forward-backward FIR band-pass of that even order), or None for the plain
+    analytic signal.
     Returns a list of dicts with [nbands, n_k, n_k] tensors.
     """
     p = _prec_id(prec)

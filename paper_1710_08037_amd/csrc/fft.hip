@@ -371,6 +371,12 @@ __global__ __launch_bounds__(nt_of(LOGM)) void chirp_kernel(const ChirpJob *jobs
 template <class R>
 __device__ inline R band_weight(BandBins bb, int k, int t)
 {
+    if (bb.fir) {  // one-sided weights times the FIR's zero-phase gain |H|^2
+        if (2 * k > t)
+            return (R)0;
+        const R one_sided = (k == 0 || 2 * k == t) ? (R)1 : (R)2;
+        return one_sided * ((const R *)bb.w)[k];
+    }
     if (bb.klo < 0)
         return k == 0 ? (R)1 : (2 * k < t ? (R)2 : (2 * k == t ? (R)1 : (R)0));
     return (k >= bb.klo && k <= bb.khi) ? (R)2 : (R)0;
@@ -791,6 +797,45 @@ hipError_t launch_twiddles(bool f64, void *tab, int logm, hipStream_t s)
         twiddle_kernel<double><<<grid, 256, 0, s>>>((cx<double> *)tab, logm);
     else
         twiddle_kernel<float><<<grid, 256, 0, s>>>((cx<float> *)tab, logm);
+    return hipGetLastError();
+}
+
+namespace {
+
+// |H(e^{i theta})|^2 = A(theta)^2, A = c_0 + 2 sum_{j=1..half} c_j cos(j theta),
+// theta = 2 pi k / t, by Clenshaw's recurrence in FP64 (no trigonometry inside
+// the sum).
+template <class R>
+__global__ __launch_bounds__(256) void fir_weights_kernel(const FirJob *jobs)
+{
+    const FirJob j = jobs[blockIdx.y];
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (2 * k > j.t)
+        return;
+    const double cs = cospi(2.0 * (double)k / (double)j.t);
+    double b1 = 0.0, b2 = 0.0;
+    for (int m = j.half; m >= 1; --m) {
+        const double b0 = j.c[m] + 2.0 * cs * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    const double amp = j.c[0] + 2.0 * (b1 * cs - b2);  // b1 cos - b2 = sum_{m>=1} c_m cos(m theta)
+    ((R *)j.w)[k] = (R)(amp * amp);
+}
+
+}  // namespace
+
+hipError_t launch_fir_weights(bool f64, const FirJob *jobs, int njobs, int max_t, hipStream_t s)
+{
+    if (njobs <= 0)
+        return hipSuccess;
+    if (njobs > 65535 || max_t < 1)
+        return hipErrorInvalidValue;
+    dim3 grid((unsigned)((max_t / 2 + 1 + 255) / 256), (unsigned)njobs);
+    if (f64)
+        fir_weights_kernel<double><<<grid, 256, 0, s>>>(jobs);
+    else
+        fir_weights_kernel<float><<<grid, 256, 0, s>>>(jobs);
     return hipGetLastError();
 }
 

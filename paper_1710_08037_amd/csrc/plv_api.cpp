@@ -307,12 +307,38 @@ static BandBins band_bins(int t, double fs, const plv_band *band)
     return BandBins{klo, khi};
 }
 
+// Forward-backward FIR band-pass (the paper's pre-Hilbert filter, Section
+// III, design not given there): taps c_m = ideal band-pass between f_lo and
+// f_hi at n = m - L/2 times the Hamming window 0.54 - 0.46 cos(2 pi m / L),
+// m = 0..L, scaled to unit gain at the band centre.  The taps are symmetric
+// about L/2, so H(e^{i theta}) = e^{-i theta L/2} A(theta) with the real
+// A(theta) = c_{L/2} + 2 sum_{j=1..L/2} c_{L/2+j} cos(j theta), and forward
+// then backward filtering has the zero-phase gain A^2, which the weight-table
+// kernel evaluates.  Returns c_{L/2}, ..., c_L (FP64).
+static std::vector<double> fir_half_taps(const plv_band &band, double fs)
+{
+    const int L = band.fir_order, half = L / 2;
+    const double pi = 3.141592653589793238462643383279502884;
+    const double lo = band.f_lo / fs, hi = band.f_hi / fs, mid = 0.5 * (lo + hi);
+    std::vector<double> c((size_t)half + 1);
+    double gain = 0.0;
+    for (int j = 0; j <= half; ++j) {
+        const double n = (double)j;
+        const double ideal = j == 0 ? 2.0 * (hi - lo) : (std::sin(2.0 * pi * hi * n) - std::sin(2.0 * pi * lo * n)) / (pi * n);
+        c[j] = ideal * (0.54 - 0.46 * std::cos(2.0 * pi * (double)(half + j) / (double)L));
+        gain += (j == 0 ? 1.0 : 2.0) * c[j] * std::cos(2.0 * pi * mid * n);
+    }
+    for (double &v : c)
+        v /= gain;
+    return c;
+}
+
 // Direct synthesis of a band costs about 4 K + 12 operations per output
 // sample (K bins); the inverse transform about (2.5 log2 M + 6) M / t per
 // sample, twice for a Bluestein length.  The cheaper one is taken.
 static bool direct_band(const FftPlan &f, BandBins bb)
 {
-    if (bb.klo < 0 || !f.has_xbins)
+    if (bb.klo < 0 || bb.fir || !f.has_xbins)
         return false;  // plain analytic signal: every positive bin
     const int k = bb.khi >= bb.klo ? bb.khi - bb.klo + 1 : 0;
     if (k > DIRECT_KMAX)
@@ -362,7 +388,13 @@ static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const pl
         h.xbins = f.has_xbins ? ws + f.xbin_off : nullptr;
         hp[q] = h;
         for (int b = 0; b < nbands; ++b) {
-            BandBins bb = band_bins(f.t, fs, bands ? &bands[b] : nullptr);
+            BandBins bb{};
+            if (bands && bands[b].fir_order > 0) {
+                bb.fir = 1;  // every bin weighted: inverse transform
+                bb.w = ws + plan.lens[f.len_index].firw_off[b];
+            } else {
+                bb = band_bins(f.t, fs, bands ? &bands[b] : nullptr);
+            }
             // (the adjoint kernel takes every band through the transform)
             bb.direct = direct_band(f, bb) ? 1 : 0;
             any_direct = any_direct || bb.direct;
@@ -383,6 +415,18 @@ static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const pl
                 for (int64_t i = 0; i < probs[q].n; ++i)
                     rows[r++] = RowRef{(int32_t)q, (int32_t)i};
         class_count.push_back((int)r - class_start.back());
+    }
+    // FIR bands: half of the (symmetric) taps, and a weight-table job per row length
+    FirJob *fj = (FirJob *)(blob.data() + plan.firjob_off);
+    int nj = 0;
+    for (int b = 0; bands && b < nbands; ++b) {
+        if (bands[b].fir_order <= 0)
+            continue;
+        const std::vector<double> c = fir_half_taps(bands[b], fs);
+        memcpy(blob.data() + plan.fir_r_off[b], c.data(), c.size() * sizeof(double));
+        for (const LenPlan &l : plan.lens)
+            fj[nj++] = FirJob{l.t, bands[b].fir_order / 2, (const double *)(ws + plan.fir_r_off[b]),
+                              ws + l.firw_off[b]};
     }
     for (size_t c = 0; c < plan.lens.size(); ++c) {
         const LenPlan &l = plan.lens[c];
@@ -419,6 +463,12 @@ static hipError_t launch_fft_setup(const Plan &plan, uint8_t *ws, hipStream_t s,
             return e;
         ++launches;
         c = d;
+    }
+    if (plan.nfirjobs > 0) {
+        if ((e = launch_fir_weights(f64, (const FirJob *)(ws + plan.firjob_off), plan.nfirjobs, plan.fir_max_t,
+                                    s)) != hipSuccess)
+            return e;
+        ++launches;
     }
     return hipSuccess;
 }
@@ -726,9 +776,12 @@ plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, 
     if (!ctx)
         return PLV_ERR_INVALID_ARG;
     if (bands) {
-        for (int32_t b = 0; b < nbands; ++b)
+        for (int32_t b = 0; b < nbands; ++b) {
             if ((bands[b].f_lo != 0.0 || bands[b].f_hi != 0.0) && !(fs > 0.0 && std::isfinite(fs)))
                 return fail(ctx, PLV_ERR_INVALID_ARG, "a band-pass band needs a finite sampling rate fs > 0");
+            if (bands[b].fir_order > 0 && !(bands[b].f_hi <= 0.5 * fs))
+                return fail(ctx, PLV_ERR_INVALID_ARG, "band %d: an FIR band needs f_hi <= fs / 2", (int)b);
+        }
     }
     Plan plan;
     plv_status st = begin(ctx, PLV_OP_FROM_REAL, prec, probs, nprob, bands, nbands, ws, ws_bytes, plan);
@@ -908,9 +961,12 @@ plv_status plv_backward(plv_ctx *ctx, plv_prec prec, plv_input kind, const plv_p
         return fail(ctx, PLV_ERR_INVALID_ARG, "grads is NULL");
     const bool real = kind == PLV_INPUT_REAL;
     if (real && bands) {
-        for (int32_t b = 0; b < nbands; ++b)
+        for (int32_t b = 0; b < nbands; ++b) {
             if ((bands[b].f_lo != 0.0 || bands[b].f_hi != 0.0) && !(fs > 0.0 && std::isfinite(fs)))
                 return fail(ctx, PLV_ERR_INVALID_ARG, "a band-pass band needs a finite sampling rate fs > 0");
+            if (bands[b].fir_order > 0 && !(bands[b].f_hi <= 0.5 * fs))
+                return fail(ctx, PLV_ERR_INVALID_ARG, "band %d: an FIR band needs f_hi <= fs / 2", (int)b);
+        }
     }
     Plan plan;
     const plv_op op = real ? PLV_OP_BACKWARD_REAL : PLV_OP_BACKWARD_ANALYTIC;

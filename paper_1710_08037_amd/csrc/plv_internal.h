@@ -198,7 +198,18 @@ constexpr int DIRECT_KMAX = 48;
 // direct = 1: synthesise the band from its bins instead of an inverse FFT.
 struct BandBins {
     int32_t klo, khi;
-    int32_t direct, pad_;
+    int32_t direct;
+    int32_t fir;          // 1: forward-backward FIR band: weights = one-sided x w[k]
+    const void *w;        // FIR: |H|^2 at bins k = 0..t/2 of the row length (R precision)
+};
+
+// One FIR weight table: w[k] = |H(exp(2 pi i k / t))|^2 = A(theta)^2, k = 0..t/2,
+// A(theta) = c[0] + 2 sum_{j=1..half} c[j] cos(j theta), c = the upper half of
+// the filter's symmetric taps (FP64, c[0] the centre tap).
+struct FirJob {
+    int32_t t, half;
+    const double *c;
+    void *w;
 };
 
 struct RowRef {
@@ -280,6 +291,8 @@ constexpr int FFT_MAXLOG_F64 = 12;  // M <= 4096 complex FP64
 hipError_t launch_twiddles(bool f64, void *tab, int logm, hipStream_t s);
 // jobs: device array of njobs set-ups that all have this logm
 hipError_t launch_chirps(bool f64, int logm, const ChirpJob *jobs, int njobs, hipStream_t s);
+// FIR weight tables; max_t = the longest row length among the jobs
+hipError_t launch_fir_weights(bool f64, const FirJob *jobs, int njobs, int max_t, hipStream_t s);
 // rows of a.rows all have FFT size a.logm; the grid is sized from cus and the
 // kernel's occupancy
 hipError_t launch_hilbert(int mode, const HilbertArgs &a, int cus, hipStream_t s);

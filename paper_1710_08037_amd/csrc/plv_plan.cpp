@@ -147,11 +147,19 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
             return PLV_ERR_INVALID_ARG;
         }
         if (bands) {
-            for (int b = 0; b < nbands; ++b)
+            for (int b = 0; b < nbands; ++b) {
                 if (!(bands[b].f_lo >= 0.0) || !(bands[b].f_hi >= bands[b].f_lo)) {
                     why = msg("band %lld: need 0 <= f_lo <= f_hi", b);
                     return PLV_ERR_INVALID_ARG;
                 }
+                const int32_t L = bands[b].fir_order;
+                if (bands[b].reserved != 0 || L < 0 || L > PLV_FIR_MAX_ORDER || (L & 1) ||
+                    (L > 0 && !(bands[b].f_hi > bands[b].f_lo))) {
+                    why = msg("band %lld: fir_order must be 0 or even in [2, %d] with f_lo < f_hi, reserved 0", b,
+                              PLV_FIR_MAX_ORDER);
+                    return PLV_ERR_INVALID_ARG;
+                }
+            }
         } else if (nbands != 1) {
             why = "bands == NULL requires nbands == 1";
             return PLV_ERR_INVALID_ARG;
@@ -334,6 +342,20 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         off += align256(plan.lens.size() * sizeof(ChirpJob));
         plan.synth_off = off;
         off += align256((size_t)(nprob + 1) * sizeof(int32_t));
+        // FIR bands: the taps' autocorrelation per band, and one weight-table
+        // job per (row length, band); the tables themselves follow below
+        std::vector<int> fir_bands;
+        for (int b = 0; bands && b < nbands; ++b)
+            if (bands[b].fir_order > 0)
+                fir_bands.push_back(b);
+        plan.fir_r_off.assign((size_t)nbands, 0);
+        for (int b : fir_bands) {
+            plan.fir_r_off[b] = off;
+            off += align256((size_t)(bands[b].fir_order + 1) * sizeof(double));
+        }
+        plan.nfirjobs = (int)(plan.lens.size() * fir_bands.size());
+        plan.firjob_off = off;
+        off += align256((size_t)plan.nfirjobs * sizeof(FirJob));
         plan.tables_bytes = off;
         for (int lg : plan.tw_logm) {
             plan.tw_off.push_back(off);
@@ -348,6 +370,13 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
                 l.bhat_off = off;
                 off += align256((size_t)(1 << l.logm) * csz);
             }
+            l.firw_off.assign((size_t)nbands, 0);
+            for (int b : fir_bands) {
+                l.firw_off[b] = off;
+                off += align256((size_t)(l.t / 2 + 1) * (csz / 2));
+            }
+            if (!fir_bands.empty())
+                plan.fir_max_t = std::max(plan.fir_max_t, l.t);
         }
         // band-pass bands may be synthesised from their bins: a slot of
         // DIRECT_KMAX bins per row and band (fs, and so the bin counts, are

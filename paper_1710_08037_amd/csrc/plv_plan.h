@@ -49,6 +49,7 @@ struct LenPlan {
     int t = 0, logm = 0;
     bool blue = false;
     size_t roots_off = 0, chirp_off = 0, bhat_off = 0;  // chirp/bhat: Bluestein only
+    std::vector<size_t> firw_off;  // per band: FIR weight table of this length (0: not an FIR band)
 };
 
 struct Plan {
@@ -69,6 +70,9 @@ struct Plan {
     std::vector<LenPlan> lens;                // distinct row lengths, ordered by (logm, t)
     size_t hp_off = 0, bin_off = 0, row_off = 0, job_off = 0;
     size_t synth_off = 0;  // band synthesis: running work-group counts [nprob + 1]
+    std::vector<size_t> fir_r_off;  // per band: the FIR taps' autocorrelation (FP64, in the tables)
+    size_t firjob_off = 0;          // FirJob per (row length, FIR band), in the tables
+    int nfirjobs = 0, fir_max_t = 0;
     size_t nrows = 0;
     size_t total = 0;
 };
