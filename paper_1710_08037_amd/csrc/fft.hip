@@ -368,10 +368,10 @@ __global__ __launch_bounds__(nt_of(LOGM)) void chirp_kernel(const ChirpJob *jobs
 }
 
 // ------------------------------------------------------------- forward --
-template <class R>
+template <class R, bool FIR>
 __device__ inline R band_weight(BandBins bb, int k, int t)
 {
-    if (bb.fir) {  // one-sided weights times the FIR's zero-phase gain |H|^2
+    if (FIR && bb.fir) {  // one-sided weights times the FIR's zero-phase gain |H|^2
         if (2 * k > t)
             return (R)0;
         const R one_sided = (k == 0 || 2 * k == t) ? (R)1 : (R)2;
@@ -527,7 +527,9 @@ __global__ __launch_bounds__(256) void band_synth_kernel(HilbertArgs a, int mode
     }
 }
 
-template <class R, int LOGM>
+// FIR: the call has forward-backward FIR bands (weights from tables); the
+// variant without them keeps the mask path's registers.
+template <class R, int LOGM, bool FIR>
 __global__ __launch_bounds__(nt_of(LOGM)) __attribute__((amdgpu_waves_per_eu((LOGM == 12 || LOGM == 11) ? 4 : 1))) void hilbert_kernel(HilbertArgs a, int mode)
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
@@ -603,7 +605,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) __attribute__((amdgpu_waves_per_eu((LO
             if (!hp.blue) {
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
-                    v[e] = cscale(X[e], band_weight<R>(bb, tid0 + e * NTA, t));
+                    v[e] = cscale(X[e], band_weight<R, FIR>(bb, tid0 + e * NTA, t));
                 fft_lds<R, LOGM, true>(v, buf, ptab, act);
                 const R inv_t = (R)1 / (R)t;
                 store_band<R>(mode, g, hp, rr.row, [&](int n) { return cscale(buf[lpad(n)], inv_t); });
@@ -613,7 +615,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) __attribute__((amdgpu_waves_per_eu((LO
                 for (int e = 0; e < PER; ++e) {
                     const int n = tid0 + e * NTA;
                     // X is 0 at n >= t, so the clamped chirp index changes nothing
-                    v[e] = cconj(cmul(cscale(X[e], band_weight<R>(bb, n, t)), gld(ch, min(n, t - 1))));
+                    v[e] = cconj(cmul(cscale(X[e], band_weight<R, FIR>(bb, n, t)), gld(ch, min(n, t - 1))));
                 }
                 fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
@@ -634,7 +636,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) __attribute__((amdgpu_waves_per_eu((LO
 // DFT(zbar_b))), zbar_b being 0 outside the window.  The spectrum sum S stays
 // in registers (natural pattern); with a single band (ONE) it is the band's
 // own spectrum and needs no second register array.
-template <class R, int LOGM, bool ONE>
+template <class R, int LOGM, bool ONE, bool FIR>
 __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArgs a)
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
@@ -674,7 +676,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
                 fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
-                    v[e] = cscale(buf[pat_addr<LOGM>(tid0, e)], band_weight<R>(bb, tid0 + e * NTA, t));
+                    v[e] = cscale(buf[pat_addr<LOGM>(tid0, e)], band_weight<R, FIR>(bb, tid0 + e * NTA, t));
             } else {
 #pragma unroll
                 for (int e = 0; e < PER; ++e) {
@@ -691,7 +693,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
                 for (int e = 0; e < PER; ++e) {
                     const int k = tid0 + e * NTA;
                     const cx<R> d = cmul(cconj(gld(ch, min(k, t - 1))), buf[pat_addr<LOGM>(tid0, e)]);
-                    v[e] = cscale(d, k < t ? band_weight<R>(bb, k, t) * invm : (R)0);
+                    v[e] = cscale(d, k < t ? band_weight<R, FIR>(bb, k, t) * invm : (R)0);
                 }
             }
             if constexpr (!ONE) {
@@ -749,15 +751,26 @@ hipError_t launch_sized(int kind, int mode, const HilbertArgs *ha, const ChirpJo
     if (kind == 0) {
         chirp_kernel<R, LOGM><<<n, NT, 0, s>>>(jobs);
     } else if (kind == 1) {
-        const int nwg = grid_for(hilbert_kernel<R, LOGM>, NT, ha->nrows, cus);
-        hilbert_kernel<R, LOGM><<<nwg, NT, 0, s>>>(*ha, mode);
-    } else {
-        if (ha->nbands == 1) {
-            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true>, NT, ha->nrows, cus);
-            hilbert_adjoint_kernel<R, LOGM, true><<<nwg, NT, 0, s>>>(*ha);
+        if (ha->fir) {
+            const int nwg = grid_for(hilbert_kernel<R, LOGM, true>, NT, ha->nrows, cus);
+            hilbert_kernel<R, LOGM, true><<<nwg, NT, 0, s>>>(*ha, mode);
         } else {
-            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false>, NT, ha->nrows, cus);
-            hilbert_adjoint_kernel<R, LOGM, false><<<nwg, NT, 0, s>>>(*ha);
+            const int nwg = grid_for(hilbert_kernel<R, LOGM, false>, NT, ha->nrows, cus);
+            hilbert_kernel<R, LOGM, false><<<nwg, NT, 0, s>>>(*ha, mode);
+        }
+    } else {
+        if (ha->nbands == 1 && !ha->fir) {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true, false>, NT, ha->nrows, cus);
+            hilbert_adjoint_kernel<R, LOGM, true, false><<<nwg, NT, 0, s>>>(*ha);
+        } else if (ha->nbands == 1) {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true, true>, NT, ha->nrows, cus);
+            hilbert_adjoint_kernel<R, LOGM, true, true><<<nwg, NT, 0, s>>>(*ha);
+        } else if (!ha->fir) {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false, false>, NT, ha->nrows, cus);
+            hilbert_adjoint_kernel<R, LOGM, false, false><<<nwg, NT, 0, s>>>(*ha);
+        } else {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false, true>, NT, ha->nrows, cus);
+            hilbert_adjoint_kernel<R, LOGM, false, true><<<nwg, NT, 0, s>>>(*ha);
         }
     }
     return hipGetLastError();

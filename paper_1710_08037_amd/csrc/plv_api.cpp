@@ -530,6 +530,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             ha.logm = plan.tw_logm[c];
             ha.gd = (const GramDesc *)(ws + plan.desc_off);
             ha.nbands = nbands;
+            ha.fir = plan.nfirjobs > 0 ? 1 : 0;
             if ((e = launch_hilbert(mode, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal kernel launch");
             tm.launched();
@@ -542,6 +543,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             ha.bins = (const BandBins *)(ws + plan.bin_off);
             ha.gd = (const GramDesc *)(ws + plan.desc_off);
             ha.nbands = nbands;
+            ha.fir = plan.nfirjobs > 0 ? 1 : 0;
             ha.nprob = (int32_t)plan.fft.size();
             ha.synth_prefix = (const int32_t *)(ws + plan.synth_off);
             if ((e = launch_band_synth(mode, ha, (int)synth_jobs, s)) != hipSuccess)
@@ -831,6 +833,7 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
     ha.bins = (const BandBins *)(ws + plan.bin_off);
     ha.gd = (const GramDesc *)(ws + plan.desc_off);
     ha.nbands = nbands;
+    ha.fir = plan.nfirjobs > 0 ? 1 : 0;
     if (real) {
         // analytic signal of the window, kept unnormalised in zbuf
         int nl = 0;

@@ -226,6 +226,8 @@ struct HilbertArgs {
     int32_t nbands;       // bands per problem (the same for every problem of a call)
     int32_t nprob;        // band synthesis: problems, and the running work-group counts
     const int32_t *synth_prefix;  //   [nprob + 1] of the problems (see band_synth_kernel)
+    int32_t fir;          // some band of the call is an FIR band (selects the kernel variant)
+    int32_t pad2_;
 };
 
 // Set-up for one distinct row length t: its root table, and for a Bluestein
