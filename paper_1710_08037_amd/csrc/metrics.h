@@ -7,7 +7,12 @@
 //   iPLV  = |Im G|                          (Section II.C, Eq. 13)
 //   ciPLV = |Im G| / sqrt((1-Re)(1+Re))     (Eq. 14; FP64 radicand, 0 if <= 0)
 //
-// written at (i, j) and (j, i); the diagonal gets PLV = 1, iPLV = ciPLV = 0
+// The ciPLV radicand is always formed in FP64.  For FP32 outputs the roots
+// are taken in FP32 (correctly rounded sqrt for PLV; hardware rsq, about
+// 1 ulp, for ciPLV): the FP64 root and division cost the single-chunk Gram
+// kernel a sixth of its time when K is short.
+//
+// Each is written at (i, j) and (j, i); the diagonal gets PLV = 1, iPLV = ciPLV = 0
 // and the computed G_ii.  G is written as G_ij and G_ji = conj(G_ij), so every
 // output is exactly symmetric (Hermitian for G).
 #pragma once
@@ -44,11 +49,27 @@ __device__ inline void store_entry(const GramDesc &d, int64_t gi, int64_t gj, do
         }
         return;
     }
-    const double am = fabs(m);
-    const double dd = (1.0 - r) * (1.0 + r);
-    const real_t vp = (real_t)sqrt(r * r + m * m);
-    const real_t vi = (real_t)am;
-    const real_t vc = (real_t)(dd > 0.0 ? am / sqrt(dd) : 0.0);
+    const double dd = (1.0 - r) * (1.0 + r);  // FP64: 1 - Re cancels
+    real_t vp, vi, vc;
+    if constexpr (MODE == M_F64) {
+        const double am = fabs(m);
+        vp = sqrt(r * r + m * m);
+        vi = am;
+        vc = dd > 0.0 ? am / sqrt(dd) : 0.0;
+    } else {
+        // FP32 outputs: the roots in FP32.  Components below 2^-60 are scaled
+        // by 2^64 first (exact both ways), so no square underflows.  A
+        // positive dd is at least about 2^-54 (1 +- Re of an FP64 Re), a
+        // normal FP32 number.
+        const float rf = (float)r, mf = (float)m;
+        const float am = fabsf(mf);
+        const bool tiny = fmaxf(fabsf(rf), am) < 0x1p-60f;
+        const float sc = tiny ? 0x1p64f : 1.0f, isc = tiny ? 0x1p-64f : 1.0f;
+        const float a = rf * sc, b = mf * sc;
+        vp = __builtin_sqrtf(fmaf(a, a, b * b)) * isc;
+        vi = am;
+        vc = dd > 0.0 ? (am * sc) * __builtin_amdgcn_rsqf((float)dd) * isc : 0.0f;
+    }
     if (plv) {
         plv[ij] = vp;
         plv[ji] = vp;

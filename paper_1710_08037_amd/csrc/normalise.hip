@@ -83,34 +83,76 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
     store4<MODE>(dst, a.plane_bytes, ur, ui);
 }
 
-// Across trials: thread (time point tau, signal i, trials k0..k0+3) reads
-// z(k, i, t0 + tau) -- consecutive threads take consecutive time points, so
-// the reads coalesce when samples are contiguous in time -- and stores the
-// four unit phasors at samples k0..k0+3 of row i of tau's planes (trials past
-// ntr are written as 0).
+// Across trials: a transpose through LDS.  A block covers TT consecutive
+// time points x TR consecutive signals x 32 consecutive trials (one sample
+// granule of the planes).  It reads z(k, i, t0 + tau) with consecutive threads
+// on consecutive time points (whole 128-byte runs when samples are contiguous
+// in time), keeps the unit phasors in LDS, then writes each time point's
+// planes with consecutive threads on 4-sample groups of one row and then on
+// rows, so a wave stores runs of 8 rows x 64 B of the stage-major planes.
+// Trials past ntr are written as 0 up to the padded length.
+struct TrialShape {
+    static constexpr int TR = 8;   // signals per block
+    static constexpr int KB = 32;  // trials (plane samples) per block
+};
+
 template <int MODE>
 __global__ __launch_bounds__(256) void trial_planes_kernel(TrialArgs a)
 {
     typedef typename std::conditional<MODE == M_F64, double, float>::type real_t;
     typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
-    const int tau = blockIdx.x * 256 + threadIdx.x;
-    if (tau >= a.ntp)
-        return;
-    const int64_t i = a.row0 + blockIdx.y;
-    const int k0 = blockIdx.z * VEC;
-    auto src = gptr((const cplx_t *)a.in + i * a.ld + (a.t0 + tau) * a.sstride);
-    real_t ur[VEC], ui[VEC];
+    constexpr int TR = TrialShape::TR, KB = TrialShape::KB;
+    constexpr int TT = MODE == M_F64 ? 8 : 16;      // time points per block
+    constexpr int NLD = TT * TR * KB / 256;         // loads per thread
+    constexpr int NST = TT * TR * (KB / 4) / 256;   // 4-sample stores per thread
+    // [tau][r][k], the 4-trial group of k swizzled by tau so that both the
+    // tau-major writes and the k-major reads spread over the banks
+    __shared__ cplx_t tile[TT * TR * KB];
+    const int tau0 = blockIdx.x * TT;
+    const int64_t i0 = (int64_t)a.row0 + (int64_t)blockIdx.y * TR;
+    const int k0 = blockIdx.z * KB;
+    const int t = threadIdx.x;
+
+    cplx_t zin[NLD];
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-        ur[v] = 0;
-        ui[v] = 0;
-        if (k0 + v < a.ntr) {
-            const cplx_t z = src[(int64_t)(k0 + v) * a.tstride];
-            unit_phasor(z.x, z.y, ur[v], ui[v]);
-        }
+    for (int q = 0; q < NLD; ++q) {
+        const int item = q * 256 + t;
+        const int tau = item % TT, p = item / TT;  // p = r * KB + k
+        const int k = p % KB, r = p / KB;
+        const int64_t i = i0 + r;
+        zin[q] = cplx_t{0, 0};
+        if (tau0 + tau < a.ntp && i < a.n && k0 + k < a.ntr)
+            zin[q] = gptr((const cplx_t *)a.in)[i * a.ld + (a.t0 + tau0 + tau) * a.sstride + (int64_t)(k0 + k) * a.tstride];
     }
-    store4<MODE>(plane_at(a.u0 + (int64_t)tau * a.gstride, a.cstride, a.chunk, a.rows, cbytes_of(MODE), i, k0),
-                 a.plane_bytes, ur, ui);
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+        const int item = q * 256 + t;
+        const int tau = item % TT, p = item / TT;
+        const int k = p % KB, r = p / KB;
+        real_t ur = 0, ui = 0;
+        if (k0 + k < a.ntr)
+            unit_phasor(zin[q].x, zin[q].y, ur, ui);
+        tile[(tau * TR + r) * KB + (((k >> 2) ^ (tau & 7)) << 2) + (k & 3)] = cplx_t{ur, ui};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NST; ++q) {
+        const int item = q * 256 + t;
+        const int kq = item % (KB / 4), r = (item / (KB / 4)) % TR, tau = item / (KB / 4 * TR);
+        const int64_t i = i0 + r;
+        if (tau0 + tau >= a.ntp || i >= a.n)
+            continue;
+        const cplx_t *src = tile + (tau * TR + r) * KB + ((kq ^ (tau & 7)) << 2);
+        real_t ur[VEC], ui[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            ur[v] = src[v].x;
+            ui[v] = src[v].y;
+        }
+        store4<MODE>(plane_at(a.u0 + (int64_t)(tau0 + tau) * a.gstride, a.cstride, a.chunk, a.rows, cbytes_of(MODE),
+                              i, k0 + kq * VEC),
+                     a.plane_bytes, ur, ui);
+    }
 }
 
 // One work-group per row: the largest |Re z| or |Im z| over the window, and
@@ -150,10 +192,15 @@ __global__ __launch_bounds__(256) void row_scale_kernel(ScaleArgs a)
 
 hipError_t launch_trial_planes(int mode, const TrialArgs &a, hipStream_t s)
 {
-    for (int r0 = 0; r0 < a.n; r0 += MAX_GRID_Y) {
+    constexpr int TR = TrialShape::TR, KB = TrialShape::KB;
+    if (a.tpad % KB != 0)
+        return hipErrorInvalidValue;
+    const int tt = mode == M_F64 ? 8 : 16;
+    for (int64_t r0 = 0; r0 < a.n; r0 += (int64_t)MAX_GRID_Y * TR) {
         TrialArgs b = a;
-        b.row0 = r0;
-        dim3 grid((a.ntp + 255) / 256, std::min(MAX_GRID_Y, a.n - r0), a.tpad / VEC);
+        b.row0 = (int32_t)r0;
+        const int64_t nblk = (a.n - r0 + TR - 1) / TR;
+        dim3 grid((a.ntp + tt - 1) / tt, (unsigned)std::min<int64_t>(MAX_GRID_Y, nblk), a.tpad / KB);
         switch (mode) {
         case M_F64: trial_planes_kernel<M_F64><<<grid, 256, 0, s>>>(b); break;
         case M_F32: trial_planes_kernel<M_F32><<<grid, 256, 0, s>>>(b); break;
