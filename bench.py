@@ -73,7 +73,7 @@ def run_gpu(z, prec, steps, warmup):
 def _source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("herk.hip", "plv_plan.cpp"):
+    for f in ("herk.hip", "metrics.h", "plv_internal.h", "plv_plan.cpp"):
         with open(os.path.join(ROOT, "paper_1710_08037_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

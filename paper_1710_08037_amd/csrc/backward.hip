@@ -61,56 +61,122 @@ __global__ __launch_bounds__(256) void planes_t_kernel(BwdPlanesArgs a)
 }
 
 // H[i][j] for j < kpad (0 for j >= n and on the diagonal), in the operand
-// format, from the forward G and the upstream gradients.
+// format, from the forward G and the upstream gradients.  A thread owns a
+// 4 x 4 block (rows i0.., columns j0..); a wave covers 32 x 32 as 8 x 8 such
+// blocks, so every read below takes whole 128-byte runs of a row.  G comes
+// from row i: the forward stores G_ji as the exact conjugate of G_ij, so
+// G_{min(i,j), max(i,j)} is G_ij or its conjugate.  The upstream weight of
+// pair {i, j} is dL/dy_ij + dL/dy_ji; the (j, i) entries are read along the
+// rows j of the transposed block, and the 4 x 4 transpose is free in
+// registers.
 template <int MODE>
 __global__ __launch_bounds__(256) void metric_adjoint_kernel(BwdMetricArgs a)
 {
     typedef typename std::conditional<MODE == M_F64, double, float>::type R;
     typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
-    const int64_t i = a.row0 + blockIdx.y;
-    const int j0 = (blockIdx.x * 256 + threadIdx.x) * 4;
-    if (j0 >= a.kpad)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)a.row0 + (int64_t)blockIdx.y * 32 + (lane >> 3) * 4;
+    const int64_t j0 = (int64_t)blockIdx.x * 128 + wave * 32 + (lane & 7) * 4;
+    if (i0 >= a.n || j0 >= a.kpad)
         return;
     const int64_t n = a.n;
     auto G = gptr((const cplx_t *)a.g);
-    auto up = gptr((const R *)a.dplv), ui_ = gptr((const R *)a.diplv), uc = gptr((const R *)a.dciplv);
-    R hr[4], hi[4];
+    R gx[4][4], gy[4][4];  // Re and Im of G_{min(i,j), max(i,j)}
+    double gr[4][4], gm[4][4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int64_t j = j0 + v;
-        hr[v] = 0;
-        hi[v] = 0;
-        if (j >= n || j == i)
-            continue;
-        const int64_t lo = i < j ? i : j, hiw = i < j ? j : i;
-        const cplx_t g = G[lo * n + hiw];
-        const double r = (double)g.x, m = (double)g.y;
-        const double sgn = m > 0.0 ? 1.0 : (m < 0.0 ? -1.0 : 0.0);
-        double gr = 0.0, gm = 0.0;
-        if (a.dplv) {
-            const double w = (double)up[lo * n + hiw] + (double)up[hiw * n + lo];
-            const double p = sqrt(r * r + m * m);
-            if (p > 0.0) {
-                gr += w * r / p;
-                gm += w * m / p;
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int64_t i = i0 + x, j = j0 + y;
+            gx[x][y] = 0;
+            gy[x][y] = 0;
+            gr[x][y] = 0.0;
+            gm[x][y] = 0.0;
+            if (i < n && j < n) {
+                const cplx_t g = G[i * n + j];
+                gx[x][y] = g.x;
+                gy[x][y] = i < j ? g.y : -g.y;
             }
         }
-        if (a.diplv)
-            gm += ((double)ui_[lo * n + hiw] + (double)ui_[hiw * n + lo]) * sgn;
-        if (a.dciplv) {
-            const double w = (double)uc[lo * n + hiw] + (double)uc[hiw * n + lo];
-            const double dd = (1.0 - r) * (1.0 + r);
-            if (dd > 0.0) {
-                const double sq = sqrt(dd);
-                gm += w * sgn / sq;
-                gr += w * fabs(m) * r / (sq * dd);
+    // w[x][y] = u(i, j) + u(j, i) over the block (0 outside n)
+    auto weights = [&](const void *up, double (&w)[4][4]) {
+        auto u = gptr((const R *)up);
+        R d[4][4], t[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                d[x][y] = 0;
+                t[y][x] = 0;
+                if (i0 + x < n && j0 + y < n) {
+                    d[x][y] = u[(i0 + x) * n + j0 + y];
+                    t[y][x] = u[(j0 + y) * n + i0 + x];
+                }
             }
-        }
-        // H_ij = Gbar_ij for i < j, conj(Gbar_ji) for i > j; scaled by 1/T
-        hr[v] = (R)(gr * a.inv_t);
-        hi[v] = (R)((i < j ? gm : -gm) * a.inv_t);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+                w[x][y] = (double)d[x][y] + (double)t[y][x];
+    };
+    double w[4][4];
+    if (a.dplv) {
+        weights(a.dplv, w);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const double r = (double)gx[x][y], m = (double)gy[x][y];
+                const double p = sqrt(r * r + m * m);
+                if (p > 0.0) {
+                    gr[x][y] += w[x][y] * r / p;
+                    gm[x][y] += w[x][y] * m / p;
+                }
+            }
     }
-    store4<MODE>(a.h + plane_off(a.rows, cbytes_of(MODE), i, j0), a.plane_bytes, hr, hi);
+    if (a.diplv) {
+        weights(a.diplv, w);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const double m = (double)gy[x][y];
+                const double sgn = m > 0.0 ? 1.0 : (m < 0.0 ? -1.0 : 0.0);
+                gm[x][y] += w[x][y] * sgn;
+            }
+    }
+    if (a.dciplv) {
+        weights(a.dciplv, w);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const double r = (double)gx[x][y], m = (double)gy[x][y];
+                const double sgn = m > 0.0 ? 1.0 : (m < 0.0 ? -1.0 : 0.0);
+                const double dd = (1.0 - r) * (1.0 + r);
+                if (dd > 0.0) {
+                    const double sq = sqrt(dd);
+                    gm[x][y] += w[x][y] * sgn / sq;
+                    gr[x][y] += w[x][y] * fabs(m) * r / (sq * dd);
+                }
+            }
+    }
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        const int64_t i = i0 + x;
+        if (i >= n)
+            break;
+        R hr[4], hi[4];
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int64_t j = j0 + y;
+            // H_ij = Gbar_ij for i < j, conj(Gbar_ji) for i > j; scaled by 1/T
+            const bool live = j < n && j != i;
+            hr[y] = live ? (R)(gr[x][y] * a.inv_t) : (R)0;
+            hi[y] = live ? (R)((i < j ? gm[x][y] : -gm[x][y]) * a.inv_t) : (R)0;
+        }
+        store4<MODE>(a.h + plane_off(a.rows, cbytes_of(MODE), i, j0), a.plane_bytes, hr, hi);
+    }
 }
 
 // zbar = i Im(conj(u) ubar) u / |z| on the window; for the full-row form
@@ -163,10 +229,10 @@ hipError_t launch_planes_t(int mode, const BwdPlanesArgs &a, hipStream_t s)
 
 hipError_t launch_metric_adjoint(int mode, const BwdMetricArgs &a, hipStream_t s)
 {
-    for (int r0 = 0; r0 < a.n; r0 += MAX_GRID_Y) {
+    for (int64_t r0 = 0; r0 < a.n; r0 += (int64_t)MAX_GRID_Y * 32) {
         BwdMetricArgs b = a;
-        b.row0 = r0;
-        dim3 grid((a.kpad / 4 + 255) / 256, std::min(MAX_GRID_Y, a.n - r0));
+        b.row0 = (int32_t)r0;
+        dim3 grid((a.kpad + 127) / 128, (unsigned)std::min<int64_t>(MAX_GRID_Y, (a.n - r0 + 31) / 32));
         switch (mode) {
         case M_F64: metric_adjoint_kernel<M_F64><<<grid, 256, 0, s>>>(b); break;
         case M_F32: metric_adjoint_kernel<M_F32><<<grid, 256, 0, s>>>(b); break;

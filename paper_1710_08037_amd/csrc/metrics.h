@@ -8,8 +8,8 @@
 //   ciPLV = |Im G| / sqrt((1-Re)(1+Re))     (Eq. 14; FP64 radicand, 0 if <= 0)
 //
 // The ciPLV radicand is always formed in FP64.  For FP32 outputs the roots
-// are taken in FP32 (correctly rounded sqrt for PLV; hardware rsq, about
-// 1 ulp, for ciPLV): the FP64 root and division cost the single-chunk Gram
+// are taken in FP32 with the hardware square root and reciprocal square root
+// (about 1 ulp each): the FP64 root and division cost the single-chunk Gram
 // kernel a sixth of its time when K is short.
 //
 // Each is written at (i, j) and (j, i); the diagonal gets PLV = 1, iPLV = ciPLV = 0
@@ -27,28 +27,15 @@ struct OutT {
     typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
 };
 
-// r, m: Re and Im of G_ij (already divided by T); gi <= gj < d.n.
+// Off-diagonal entry: r, m are Re and Im of G_ij (already divided by T),
+// ij and ji the flat indices of (i, j) and (j, i).
 template <int MODE>
-__device__ inline void store_entry(const GramDesc &d, int64_t gi, int64_t gj, double r, double m)
+__device__ inline void store_pair(const GramDesc &d, int64_t ij, int64_t ji, double r, double m)
 {
     typedef typename OutT<MODE>::real_t real_t;
     typedef typename OutT<MODE>::cplx_t cplx_t;
     auto plv = gptr((real_t *)d.plv), iplv = gptr((real_t *)d.iplv), ciplv = gptr((real_t *)d.ciplv);
     auto g = gptr((cplx_t *)d.g);
-    const int64_t n = d.n;
-    const int64_t ij = gi * n + gj, ji = gj * n + gi;
-    if (gi == gj) {
-        if (plv) plv[ij] = (real_t)1;
-        if (iplv) iplv[ij] = (real_t)0;
-        if (ciplv) ciplv[ij] = (real_t)0;
-        if (g) {
-            cplx_t v;
-            v.x = (real_t)r;
-            v.y = (real_t)m;
-            g[ij] = v;
-        }
-        return;
-    }
     const double dd = (1.0 - r) * (1.0 + r);  // FP64: 1 - Re cancels
     real_t vp, vi, vc;
     if constexpr (MODE == M_F64) {
@@ -66,7 +53,7 @@ __device__ inline void store_entry(const GramDesc &d, int64_t gi, int64_t gj, do
         const bool tiny = fmaxf(fabsf(rf), am) < 0x1p-60f;
         const float sc = tiny ? 0x1p64f : 1.0f, isc = tiny ? 0x1p-64f : 1.0f;
         const float a = rf * sc, b = mf * sc;
-        vp = __builtin_sqrtf(fmaf(a, a, b * b)) * isc;
+        vp = __builtin_amdgcn_sqrtf(fmaf(a, a, b * b)) * isc;
         vi = am;
         vc = dd > 0.0 ? (am * sc) * __builtin_amdgcn_rsqf((float)dd) * isc : 0.0f;
     }
@@ -90,6 +77,31 @@ __device__ inline void store_entry(const GramDesc &d, int64_t gi, int64_t gj, do
         v.y = (real_t)(-m);
         g[ji] = v;
     }
+}
+
+// r, m: Re and Im of G_ij (already divided by T); gi <= gj < d.n.
+template <int MODE>
+__device__ inline void store_entry(const GramDesc &d, int64_t gi, int64_t gj, double r, double m)
+{
+    typedef typename OutT<MODE>::real_t real_t;
+    typedef typename OutT<MODE>::cplx_t cplx_t;
+    const int64_t n = d.n;
+    const int64_t ij = gi * n + gj;
+    if (gi == gj) {
+        auto plv = gptr((real_t *)d.plv), iplv = gptr((real_t *)d.iplv), ciplv = gptr((real_t *)d.ciplv);
+        auto g = gptr((cplx_t *)d.g);
+        if (plv) plv[ij] = (real_t)1;
+        if (iplv) iplv[ij] = (real_t)0;
+        if (ciplv) ciplv[ij] = (real_t)0;
+        if (g) {
+            cplx_t v;
+            v.x = (real_t)r;
+            v.y = (real_t)m;
+            g[ij] = v;
+        }
+        return;
+    }
+    store_pair<MODE>(d, ij, gj * n + gi, r, m);
 }
 
 }  // namespace plv
