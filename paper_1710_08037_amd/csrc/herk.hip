@@ -505,34 +505,21 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
     }
     if (d.fused) {
         // ---- single chunk: the measures straight from the accumulators
-        // Each 16 x 16 accumulator block is classified once per wave: wholly
-        // below the diagonal or past n (skipped), wholly strictly above the
-        // diagonal and inside n (stored without per-entry tests), or mixed.
         const double inv_t = 1.0 / (double)d.t;
         const int r0 = wm * (BM / 2) + (MODE == M_F64 ? (lane >> 4) : (lane >> 4) * 4);
         constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;
         const int c0 = wn * (BM / 2) + (lane & 15);
-        const int64_t n = d.n;
 #pragma unroll
         for (int a = 0; a < NB; ++a)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int64_t bi = (int64_t)I * BM + wm * (BM / 2) + a * 16;  // block origin (wave-uniform)
-                const int64_t bj = (int64_t)J * BM + wn * (BM / 2) + b * 16;
-                if (bi >= n || bj >= n || bi > bj + 15)
-                    continue;
-                const bool inner = bi + 16 <= n && bj + 16 <= n && bi + 15 < bj;
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t gi = (int64_t)I * BM + r0 + a * 16 + r * RSTEP;
                     const int64_t gj = (int64_t)J * BM + c0 + b * 16;
-                    const double rr = (double)re[a][b][r] * inv_t, mm = (double)im[a][b][r] * inv_t;
-                    if (inner)
-                        store_pair<MODE>(d, gi * n + gj, gj * n + gi, rr, mm);
-                    else if (gi < n && gj < n && gi <= gj)
-                        store_entry<MODE>(d, gi, gj, rr, mm);
+                    if (gi < d.n && gj < d.n && gi <= gj)
+                        store_entry<MODE>(d, gi, gj, (double)re[a][b][r] * inv_t, (double)im[a][b][r] * inv_t);
                 }
-            }
         return;
     }
     // ---- chunk sum of this tile -> partial[slot][tile][re|im][BM][BM] (FP64).
