@@ -258,6 +258,32 @@ plv_status plv_trials_workspace_size(const plv_ctx *ctx, plv_prec prec, const pl
 plv_status plv_over_trials(plv_ctx *ctx, plv_prec prec, const plv_trials *p, void *ws, size_t ws_bytes,
                            void *stream);
 
+/* -------------------------------------------------------------- autotune */
+
+/* Measure the K-chunk count of a single-problem forward call (one problem, one
+ * band) on this device and keep the fastest in `ctx`.  The Gram sums over T
+ * (Eqs. 6-7) run as K-chunks, one work-group per (tile, chunk); the planner
+ * picks their number from a cost model, and this call replaces that choice by
+ * a measurement: the model's count and up to two exact splits on either side
+ * are each run once untimed and three times between HIP events on `stream`
+ * (the outputs are written as by the call itself); a count must beat the best
+ * so far by more than 1% to replace it.  Every later plan on `ctx` with the
+ * same precision, row count and padded length (plv_workspace_size included:
+ * query it again, the partial-sum slots depend on the count) uses the winner.
+ *   op: PLV_OP_FROM_ANALYTIC, PLV_OP_FROM_REAL or PLV_OP_COHERENCE; the other
+ *     arguments exactly as for that call (bands/nbands/fs are read for
+ *     PLV_OP_FROM_REAL only).  Counts whose workspace exceeds ws_bytes are
+ *     skipped.
+ *   nchunk (host, may be NULL): the count kept, or 0 when there is nothing to
+ *     choose (several problems or bands: a grouped launch gives every chunk
+ *     its own slot).
+ * Blocks the host until the trial runs have finished.  Argument errors as for
+ * the compute call; PLV_ERR_DEVICE on a failed launch or event (the previous
+ * choice is then kept).  Not part of the paper: a tuning aid for the launch. */
+plv_status plv_autotune(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                        const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes, void *stream,
+                        int32_t *nchunk);
+
 /* -------------------------------------------------------------- backward */
 
 /* Gradient of a scalar loss with respect to the input, given dL/d(outputs).

@@ -40,7 +40,7 @@ class Grad(C.Structure):
 EXPORTS = ("plv_create", "plv_destroy", "plv_status_str", "plv_last_error", "plv_version",
            "plv_timing_enable", "plv_timing_read",
            "plv_workspace_size", "plv_from_analytic", "plv_from_real", "plv_coherence",
-           "plv_trials_workspace_size", "plv_over_trials", "plv_backward")
+           "plv_trials_workspace_size", "plv_over_trials", "plv_backward", "plv_autotune")
 
 STAGES = ("hilbert", "normalise", "gram", "epilogue", "backward")
 NSTAGES = 8
@@ -99,6 +99,9 @@ def lib():
             L.plv_backward.argtypes = [P, C.c_int, C.c_int, C.POINTER(Problem), C.POINTER(Grad), C.c_int64,
                                        C.POINTER(Band), C.c_int32, C.c_double, P, C.c_size_t, P]
             L.plv_backward.restype = C.c_int
+            L.plv_autotune.argtypes = [P, C.c_int, C.c_int, C.POINTER(Problem), C.c_int64, C.POINTER(Band), C.c_int32,
+                                       C.c_double, P, C.c_size_t, P, C.POINTER(C.c_int32)]
+            L.plv_autotune.restype = C.c_int
             _LIB = L
     return _LIB
 

@@ -219,6 +219,32 @@ def from_real(x, fs, bands=None, prec="split_bf16", window=None, want=ALL, want_
     return from_real_batch([x], fs, bands, prec, None if window is None else [window], want, want_g)[0]
 
 
+def autotune(x, prec="split_bf16", window=None, fs=None, bands=None, coherence=False):
+    """Measure the K-chunk count of one problem's forward call through
+    plv_autotune and keep it for later calls of the same shape on this device.
+
+    x: complex rows (analytic signals; Fourier coefficients with coherence=True)
+    or real rows (then fs and at most one band).  Returns the count kept, or 0
+    when there is nothing to choose.  Blocks until the trial runs finish.
+    """
+    p = _prec_id(prec)
+    dev = x.device
+    real = not x.is_complex()
+    barr, nb = _abi.bands(bands) if real else (None, 1)
+    rd = torch.float64 if p == 0 else torch.float32
+    cd = torch.complex128 if p == 0 else torch.complex64
+    o = _outputs(x.shape[0], nb, rd, cd, dev, ALL, False)
+    arr = _abi.problems([_problem(x, window, o)])
+    op = _abi.OP_FROM_REAL if real else (_abi.OP_COHERENCE if coherence else _abi.OP_FROM_ANALYTIC)
+    ctx = context(dev)
+    ws = _workspace(ctx, op, p, arr, barr, nb, dev)
+    chosen = C.c_int32(0)
+    _abi.check(_abi.lib().plv_autotune(ctx.handle, op, p, arr, 1, barr, nb, float(fs or 0.0),
+                                       C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev), C.byref(chosen)),
+               ctx.handle)
+    return chosen.value
+
+
 def timing_enable(on=True, device=None):
     """Turn per-stage GPU timing (HIP events on the call's stream) on or off."""
     ctx = context(device)

@@ -38,6 +38,7 @@ struct plv_ctx {
     bool timing = false;
     std::vector<TimingRec> recs;   // recorded, not yet read
     std::vector<hipEvent_t> pool;  // idle events
+    plv::TuneMap tune;             // measured K-chunk counts (plv_autotune)
 };
 
 namespace {
@@ -254,7 +255,7 @@ plv_status plv_workspace_size(const plv_ctx *ctx, plv_op op, plv_prec prec, cons
     Plan plan;
     std::string why;
     plv_status st = make_plan(ctx ? ctx->cus : 256, ctx ? ctx->occ : nullptr, op, prec, probs, nprob, bands, nbands,
-                              plan, why);
+                              plan, why, ctx ? &ctx->tune : nullptr);
     if (st != PLV_OK) {
         if (ctx)
             const_cast<plv_ctx *>(ctx)->err = why;
@@ -274,7 +275,7 @@ static plv_status begin(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_proble
     if (ctx->device < 0)
         return fail(ctx, PLV_ERR_INVALID_ARG, "host-only context cannot compute");
     std::string why;
-    plv_status st = make_plan(ctx->cus, ctx->occ, op, prec, probs, nprob, bands, nbands, plan, why);
+    plv_status st = make_plan(ctx->cus, ctx->occ, op, prec, probs, nprob, bands, nbands, plan, why, &ctx->tune);
     if (st != PLV_OK)
         return fail(ctx, st, "%s", why.c_str());
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
@@ -989,6 +990,111 @@ plv_status plv_backward(plv_ctx *ctx, plv_prec prec, plv_input kind, const plv_p
     }
     return enqueue_backward(ctx, plan, probs, grads, real ? bands : nullptr, real ? (bands ? nbands : 1) : 1, fs,
                             (uint8_t *)ws, (hipStream_t)stream);
+}
+
+// Measures the K-chunk count of a single-problem forward call: the planner's
+// choice and up to two exact splits on either side, each run once untimed and
+// three times between HIP events on the caller's stream; a count replaces the
+// best so far only when it is more than 1% faster.  The winner is kept in the
+// context for every later plan of the same (precision, rows, padded length).
+plv_status plv_autotune(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                        const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes, void *stream,
+                        int32_t *nchunk)
+{
+    if (!ctx)
+        return PLV_ERR_INVALID_ARG;
+    if (nchunk)
+        *nchunk = 0;
+    if (op != PLV_OP_FROM_ANALYTIC && op != PLV_OP_FROM_REAL && op != PLV_OP_COHERENCE)
+        return fail(ctx, PLV_ERR_INVALID_ARG, "autotune takes a forward op");
+    const bool real = op == PLV_OP_FROM_REAL;
+    Plan plan;
+    plv_status st = begin(ctx, op, prec, probs, nprob, real ? bands : nullptr, real ? nbands : 1, ws, ws_bytes, plan);
+    if (st != PLV_OK)
+        return st;
+    std::vector<int> counts;
+    chunk_counts(plan, counts);
+    if (counts.empty())
+        return PLV_OK;  // grouped launch: one pass, every chunk its own slot
+    const auto key = tune_key(plan);
+    const int cur = plan.grams[0].nchunk;
+    const size_t at = (size_t)(std::lower_bound(counts.begin(), counts.end(), cur) - counts.begin());
+    std::vector<int> cand{cur};
+    for (size_t d = 1; d <= 2; ++d) {
+        if (at >= d)
+            cand.push_back(counts[at - d]);
+        if (at + d < counts.size())
+            cand.push_back(counts[at + d]);
+    }
+    const hipStream_t s = (hipStream_t)stream;
+    auto run = [&]() -> plv_status {
+        if (op == PLV_OP_FROM_ANALYTIC)
+            return plv_from_analytic(ctx, prec, probs, nprob, ws, ws_bytes, stream);
+        if (op == PLV_OP_COHERENCE)
+            return plv_coherence(ctx, prec, probs, nprob, ws, ws_bytes, stream);
+        return plv_from_real(ctx, prec, probs, nprob, bands, nbands, fs, ws, ws_bytes, stream);
+    };
+    const auto old = ctx->tune.find(key);
+    const bool had = old != ctx->tune.end();
+    const int old_nc = had ? old->second : 0;
+    auto restore = [&]() {
+        if (had)
+            ctx->tune[key] = old_nc;
+        else
+            ctx->tune.erase(key);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        if (e0)
+            (void)hipEventDestroy(e0);
+        return hip_fail(ctx, e, "hipEventCreate");
+    }
+    const bool timing = ctx->timing;
+    ctx->timing = false;  // the trial runs stay out of the stage timings
+    int best = 0;
+    float best_ms = 0.0f;
+    for (int nc : cand) {
+        ctx->tune[key] = nc;
+        Plan trial;
+        std::string why;
+        if (make_plan(ctx->cus, ctx->occ, op, prec, probs, nprob, real ? bands : nullptr, real ? nbands : 1, trial, why,
+                      &ctx->tune) != PLV_OK ||
+            trial.total > ws_bytes || trial.grams[0].nchunk != nc)
+            continue;  // needs more workspace than the caller gave
+        if ((st = run()) != PLV_OK)
+            break;
+        if ((e = hipEventRecord(e0, s)) != hipSuccess)
+            break;
+        for (int r = 0; r < 3 && st == PLV_OK; ++r)
+            st = run();
+        if (st != PLV_OK)
+            break;
+        float ms = 0.0f;
+        if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+            break;
+        if (best == 0 || ms < best_ms * 0.99f) {
+            best = nc;
+            best_ms = ms;
+        }
+    }
+    ctx->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PLV_OK || e != hipSuccess) {
+        restore();
+        return st != PLV_OK ? st : hip_fail(ctx, e, "autotune timing");
+    }
+    if (best > 0)
+        ctx->tune[key] = best;
+    else
+        restore();
+    if (nchunk)
+        *nchunk = best;
+    return PLV_OK;
 }
 
 }  // extern "C"

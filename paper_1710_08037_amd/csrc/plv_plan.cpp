@@ -25,15 +25,33 @@ std::string msg(const char *fmt, long long a = 0, long long b = 0)
 // run in passes.
 constexpr double ITEM_OVERHEAD = 512.0;  // fixed cost of a work item, in samples of K
 
-void choose_chunks_single(GramPlan &g, int slots, int bm, int maxc)
+// Chunk-count bounds of choose_chunks_single: no chunk longer than maxc, none
+// shorter than MIN_CHUNK unless T itself is.
+void chunk_bounds(const GramPlan &g, int maxc, int &lo, int &hi)
+{
+    const int kgr = g.tpad / PLV_KGRAN;
+    lo = std::max(1, (g.tpad + maxc - 1) / maxc);
+    hi = std::max(lo, std::min(kgr, std::max(1, g.tpad / MIN_CHUNK)));
+}
+
+// An exact split: nc chunks of ceil(kgr / nc) granules use all nc chunks.
+bool exact_split(int kgr, int nc)
+{
+    const int per = (kgr + nc - 1) / nc;
+    return (kgr + per - 1) / per == nc;
+}
+
+// `forced` > 0: a measured chunk count (plv_autotune), taken when it is an
+// exact split within the bounds.
+void choose_chunks_single(GramPlan &g, int slots, int bm, int maxc, int forced)
 {
     // Estimated time of a chunk count: for each pass, the rounds of work-groups
     // the GPU runs (items / slots, rounded up) times the length of one item,
     // its chunk plus a fixed per-item cost (prologue, fold, partial store) in
     // samples.  Ties go to fewer chunks: fewer partial slots to write and sum.
     const int kgr = g.tpad / PLV_KGRAN;
-    const int lo = std::max(1, (g.tpad + maxc - 1) / maxc);
-    const int hi = std::max(lo, std::min(kgr, std::max(1, g.tpad / MIN_CHUNK)));
+    int lo, hi;
+    chunk_bounds(g, maxc, lo, hi);
     const size_t slot_bytes = (size_t)g.nupper * 2 * bm * bm * sizeof(double);
     const int budget = (int)std::max<size_t>(1, std::min<size_t>(INT32_MAX, PARTIAL_BUDGET / slot_bytes));
     int best = lo;
@@ -53,6 +71,8 @@ void choose_chunks_single(GramPlan &g, int slots, int bm, int maxc)
             best = nc;
         }
     }
+    if (forced >= lo && forced <= hi && exact_split(kgr, forced))
+        best = forced;
     const int per = (kgr + best - 1) / best;  // granules per chunk
     g.chunk = per * PLV_KGRAN;
     g.nchunk = (kgr + per - 1) / per;
@@ -125,7 +145,7 @@ void schedule_items(Plan &plan)
 }  // namespace
 
 plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
-                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why)
+                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why, const TuneMap *tune)
 {
     plan = Plan();
     if ((int)prec < 0 || (int)prec > 4) {
@@ -287,7 +307,13 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         plan.tile_off = off;
         off += align256(plan.ntiles * sizeof(TileRef));
     } else {
-        choose_chunks_single(plan.grams[0], slots, bm, MAX_CHUNK);
+        int forced = 0;
+        if (tune) {
+            const auto it = tune->find(tune_key(plan));
+            if (it != tune->end())
+                forced = it->second;
+        }
+        choose_chunks_single(plan.grams[0], slots, bm, MAX_CHUNK, forced);
         plan.grams[0].fused = plan.grams[0].nchunk == 1 && op != PLV_OP_COHERENCE;
         plan.has_order = true;
         plan.order_off = off;
@@ -511,6 +537,26 @@ void build_tables(const Plan &plan, const std::vector<GramDesc> &gd, std::vector
             for (int t = 0; t < d.nupper; ++t)
                 tiles.push_back(TileRef{(int32_t)q, t});
     }
+}
+
+std::tuple<int, int64_t, int64_t> tune_key(const Plan &plan)
+{
+    const GramPlan &g = plan.grams[0];
+    return std::make_tuple(plan.mode, (int64_t)g.n, (int64_t)g.tpad);
+}
+
+void chunk_counts(const Plan &plan, std::vector<int> &out)
+{
+    out.clear();
+    if (plan.grams.size() != 1 || plan.grouped)
+        return;
+    const GramPlan &g = plan.grams[0];
+    const int kgr = g.tpad / PLV_KGRAN;
+    int lo, hi;
+    chunk_bounds(g, MAX_CHUNK, lo, hi);
+    for (int nc = lo; nc <= hi; ++nc)
+        if (exact_split(kgr, nc))
+            out.push_back(nc);
 }
 
 }  // namespace plv

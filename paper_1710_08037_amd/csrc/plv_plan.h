@@ -4,7 +4,9 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "plv_internal.h"
@@ -79,8 +81,19 @@ struct Plan {
 
 // Checks the arguments and lays out the workspace.  `occ` (work-groups per CU
 // of the Gram kernel, per mode) may be NULL: then 1 is assumed.
+// K-chunk counts measured by plv_autotune for single-problem launches, keyed
+// by (mode, rows, padded length); make_plan uses them in place of its model.
+typedef std::map<std::tuple<int, int64_t, int64_t>, int> TuneMap;
+
 plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
-                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why);
+                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why,
+                     const TuneMap *tune = nullptr);
+
+// The K-chunk counts a single-problem plan can take (every chunk but the last
+// the same whole number of granules), ascending; empty for a grouped plan.
+void chunk_counts(const Plan &plan, std::vector<int> &out);
+// Key of a single-problem plan in a TuneMap.
+std::tuple<int, int64_t, int64_t> tune_key(const Plan &plan);
 
 void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd);
 // Launch order of the upper-triangle tiles of an ntile x ntile grid: blocks

@@ -108,6 +108,20 @@ def test_compute_on_host_only_context_is_rejected(host_ctx):
     assert b"host-only" in _abi.lib().plv_last_error(host_ctx)
 
 
+def test_autotune_checks_before_any_launch(host_ctx):
+    arr = _abi.problems([_prob()])
+    got = C.c_int32(-1)
+    # a backward op is not tunable; a host-only context cannot run the trials
+    st = _abi.lib().plv_autotune(host_ctx, _abi.OP_BACKWARD_ANALYTIC, 2, arr, 1, None, 1, 0.0, C.c_void_p(256),
+                                 1 << 30, None, C.byref(got))
+    assert st == 1 and got.value == 0
+    assert b"forward op" in _abi.lib().plv_last_error(host_ctx)
+    st = _abi.lib().plv_autotune(host_ctx, _abi.OP_FROM_ANALYTIC, 2, arr, 1, None, 1, 0.0, C.c_void_p(256),
+                                 1 << 30, None, C.byref(got))
+    assert st == 1 and got.value == 0
+    assert b"host-only" in _abi.lib().plv_last_error(host_ctx)
+
+
 def test_null_context_rejected():
     arr = _abi.problems([_prob()])
     assert _abi.lib().plv_from_analytic(None, 2, arr, 1, None, 0, None) == 1
