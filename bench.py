@@ -419,8 +419,11 @@ def torch_index(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    # the GPU idles while the host makes the inputs; a few warm-up steps leave
+    # the timed ones on a clock still ramping up (about 12% slower on the
+    # sensor case), so the default warms up for as many steps as it times
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--prec", default="both", choices=["both", "split_bf16", "f32"],
                     help="paths to time (both: split-BF16 for `value`, FP32 beside it)")
