@@ -21,8 +21,9 @@
  *     plv_grad, plv_band) and size outputs are HOST pointers.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Compute calls only enqueue work on it and return; results are ready
- *     when the stream has reached that point.  Descriptor arrays may be freed
- *     as soon as the call returns.
+ *     when the stream has reached that point (plv_autotune alone waits for
+ *     its trial runs).  Descriptor arrays may be freed as soon as the call
+ *     returns.
  *   - Ownership: the caller allocates and owns every device buffer, including
  *     the workspace.  Compute entry points never allocate or free device
  *     memory.  plv_create allocates only host-side state.
