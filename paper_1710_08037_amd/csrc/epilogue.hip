@@ -7,13 +7,16 @@
 // window length; then the measures of Eqs. 2, 13 and 14 at (i, j) and (j, i)
 // (metrics.h).
 //
-// Each work-group covers 1024 elements (8 rows) of one tile so that even a
-// small problem spreads over many CUs; reads of the partial sums are
+// Each work-group covers EPB = 256 elements (two rows) of one tile, one per
+// thread, so that every thread has all its slot loads in flight at once and
+// even a small problem spreads over many CUs; reads of the partial sums are
 // contiguous along j.
 #include "metrics.h"
 
 namespace plv {
 namespace {
+
+constexpr int EPB = 256;  // tile elements per work-group (one per thread)
 
 template <int MODE>
 __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
@@ -42,13 +45,12 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
     const double inv_t = 1.0 / (double)d.t;
     const int64_t n = d.n;
 
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int e = blockIdx.y * 1024 + k * 256 + threadIdx.x;
+    {
+        const int e = blockIdx.y * EPB + threadIdx.x;
         const int i = e / BM, j = e - (e / BM) * BM;
         const int64_t gi = (int64_t)I * BM + i, gj = (int64_t)J * BM + j;
         if (gi >= n || gj >= n || gi > gj)
-            continue;
+            return;
         // slots added in index order; loads issued eight at a time so the
         // sum is not a chain of dependent memory latencies
         double sr = 0.0, si = 0.0;
@@ -122,7 +124,7 @@ hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, hipStream_t s
     if (ntiles <= 0)
         return hipSuccess;
     const int bm = tile_of(mode);
-    dim3 grid(ntiles, bm * bm / 1024);
+    dim3 grid(ntiles, bm * bm / EPB);
     switch (mode) {
     case M_F64: epilogue_kernel<M_F64><<<grid, 256, 0, s>>>(a); break;
     case M_F32: epilogue_kernel<M_F32><<<grid, 256, 0, s>>>(a); break;
