@@ -20,7 +20,8 @@ constexpr int TB = 64;  // transpose block: 64 signals x 64 samples
 
 // W[s][k] = conj(u_k(s)) for s < tw, k < kpad (0 for k >= n): rows are
 // samples, K runs over signals.  Reads z coalesced along samples, writes W
-// in groups of 4 signals (one store4 each), through an LDS tile.
+// in groups of 4 signals (one store4 each) along its plane stages, through
+// an LDS tile.
 template <int MODE>
 __global__ __launch_bounds__(256) void planes_t_kernel(BwdPlanesArgs a)
 {
@@ -43,9 +44,13 @@ __global__ __launch_bounds__(256) void planes_t_kernel(BwdPlanesArgs a)
         tim[kk][ss] = ui;
     }
     __syncthreads();
-    // store: 4 consecutive signals of one sample per thread
+    // store: 4 consecutive signals of one sample per thread; consecutive
+    // threads fill one plane stage (SPS signals) of a row, then the next rows,
+    // so a wave writes one contiguous run of the stage-major planes
+    constexpr int SPS = 64 / cbytes_of(MODE);  // signals per plane stage
+    constexpr int QS = SPS / 4;                // threads per row stage
     for (int e = tid; e < TB * TB / 4; e += 256) {
-        const int ss = e / (TB / 4), kq = (e % (TB / 4)) * 4;
+        const int ss = (e / QS) % TB, kq = (e / (QS * TB)) * SPS + (e % QS) * 4;
         const int s = s0 + ss;
         // kpad is a multiple of 32, not of the 64-wide block: stop at the row end
         if (s >= a.tw || k0 + kq >= a.kpad)
