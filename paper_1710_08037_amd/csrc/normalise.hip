@@ -167,6 +167,7 @@ __global__ __launch_bounds__(256) void row_scale_kernel(ScaleArgs a)
     const int row = blockIdx.x;
     auto src = gptr((const cplx_t *)a.in + (int64_t)row * a.ld + a.t0);
     R m = 0;
+#pragma unroll 8
     for (int s = threadIdx.x; s < a.tw; s += 256) {
         const cplx_t z = src[s];
         m = fmax(m, fmax(fabs(z.x), fabs(z.y)));
