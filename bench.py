@@ -46,28 +46,45 @@ FLOP_PER_PAIR_SAMPLE = {"split_bf16": 24, "bf16": 8, "f16": 8, "f32": 8, "f64": 
 N_SIG, T_SAMP, FS = 1024, 60000, 1000.0
 
 
-def run_gpu(z, prec, steps, warmup):
+def step_times(fn, steps, warmup):
+    """Run fn() `warmup` times untimed, then `steps` times, each between its
+    own pair of events on the current stream (the stream the library
+    launches on), with per-stage timing on.  Returns (median ms per step,
+    mean ms per step, stage sums, per-call Gram launch times)."""
+    import statistics
+
     import torch
 
     import paper_1710_08037_amd as plv
 
     for _ in range(warmup):
-        plv.from_analytic(z, prec=prec)
+        fn()
     torch.cuda.synchronize()
     plv.timing_enable(True)
     plv.timing_read(reset=True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
-    start.record()
-    for _ in range(steps):
-        plv.from_analytic(z, prec=prec)
-    stop.record()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
     torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
+    per = [a.elapsed_time(b) for a, b in ev]
+    gram = [ms / max(ln, 1) for ms, ln in plv.timing_list("gram")]
     stages = plv.timing_read(reset=True)
     plv.timing_enable(False)
-    return total_ms / steps, stages
+    return statistics.median(per), sum(per) / len(per), stages, gram
+
+
+def run_gpu(z, prec, steps, warmup):
+    import paper_1710_08037_amd as plv
+
+    return step_times(lambda: plv.from_analytic(z, prec=prec), steps, warmup)
+
+
+# arithmetic type each precision mode computes in (the Gram's MFMA inputs)
+DTYPE = {"split_bf16": "bf16x3 (split hi+lo, fp32 accumulate)", "bf16": "bf16", "f16": "f16", "f32": "f32",
+         "f64": "f64"}
 
 
 def _source_hash():
@@ -103,9 +120,13 @@ def issued_flops(prec, n, t):
     return FLOP_PER_PAIR_SAMPLE[prec] * (ntile * (ntile + 1) // 2) * bm * bm * (-(-t // 32) * 32)
 
 
-def roofline(prec, n, t, stages):
-    ms, calls, launches = stages["gram"]
-    per_launch_s = ms / max(launches, 1) / 1e3
+def roofline(prec, n, t, stages, gram_launch_ms):
+    """Roofline of the Gram kernel from the median of its per-launch times
+    (HIP events recorded by the library on the stream it launches on)."""
+    import statistics
+
+    per_launch_s = statistics.median(gram_launch_ms) / 1e3
+    mean_launch_s = stages["gram"][0] / max(stages["gram"][2], 1) / 1e3
     flops = FLOP_PER_PAIR_SAMPLE[prec] * (n * (n - 1) // 2) * t
     achieved = flops / per_launch_s / 1e12
     peak = PEAK_TFLOPS[prec]
@@ -114,8 +135,51 @@ def roofline(prec, n, t, stages):
             "frac": round(achieved / peak, 4),
             "traffic": measured_traffic("herk_kernel<%s>" % prec, "n%d_t%d" % (n, t)),
             "kernel": "herk_kernel<%s>" % prec, "kernel_ms": round(per_launch_s * 1e3, 4),
+            "kernel_ms_mean": round(mean_launch_s * 1e3, 4),
             "flop_per_pair_sample": FLOP_PER_PAIR_SAMPLE[prec],
+            "useful_frac_8flop": round(8 * (n * (n - 1) // 2) * t / per_launch_s / 1e12 / peak, 4),
             "issued_achieved": round(issued_tf, 2), "issued_frac": round(issued_tf / peak, 4)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_gram_rate(z_np, budget_s=4.0):
+    """The paper's own matrix method on this host, as context: FP64
+    U @ U^H / T through torch's CPU BLAS on all cores (unit phasors made
+    with numpy), on the first R rows, R sized for about `budget_s`.
+    Returns (pair-samples/s, rows, threads, seconds)."""
+    import numpy as np
+    import torch
+
+    t = z_np.shape[1]
+
+    def run(r):
+        u = z_np[:r].astype(np.complex128)
+        u = u / np.where(np.abs(u) > 0, np.abs(u), 1.0)
+        ut = torch.from_numpy(u)
+        t0 = time.perf_counter()
+        g = ut @ ut.conj().T / t
+        dt = time.perf_counter() - t0
+        del g
+        return dt
+
+    r = min(z_np.shape[0], 128)
+    dt = run(r)
+    rate = r * (r - 1) / 2 * t / dt
+    r2 = int(min(z_np.shape[0], max(r, math.sqrt(2 * rate * budget_s / t))))
+    if r2 > r:
+        r, dt = r2, run(r2)
+        rate = r * (r - 1) / 2 * t / dt
+    return rate, r, torch.get_num_threads(), dt
 
 
 def cpu_baseline(z_np, gpu_out, budget_s=15.0):
@@ -157,32 +221,29 @@ def cpu_baseline(z_np, gpu_out, budget_s=15.0):
                       "ciplv": float(np.abs(out["ciplv"][a, b] - cp).max())}
     base = {"value": round(value, 1), "unit": "pair-samples/s", "cores": nthreads, "kind": "oracle",
             "sample": "all %d pairs among the first %d signals x %d samples of the same input, %.1f s"
-                      % (len(pr), r, t, dt)}
+                      % (len(pr), r, t, dt), "cpu_model": cpu_model()}
+    # the same oracle on one core, on a smaller sample
+    r1 = int(max(16, min(r, math.sqrt(2 * (value / nthreads) * 4.0 / t))))
+    zs = z_np[:r1].astype(np.complex128)
+    pr1 = oracle.upper_pairs(r1)
+    t0 = time.perf_counter()
+    oracle.pair_means(oracle.phase(zs), pr1, 1)
+    dt1 = time.perf_counter() - t0
+    base["one_core"] = {"value": round(len(pr1) * t / dt1, 1), "cores": 1,
+                        "sample": "all %d pairs among the first %d signals, %.1f s" % (len(pr1), r1, dt1)}
+    rate, rg, thr, dtg = cpu_gram_rate(z_np)
+    base["cpu_gram"] = {"value": round(rate, 1), "unit": "pair-samples/s", "threads": thr,
+                        "kind": "FP64 U @ U^H / T, torch CPU BLAS (the paper's matrix method, context only)",
+                        "sample": "first %d signals x %d samples, %.2f s" % (rg, t, dtg)}
     return base, errs
 
 
 def timed(fn, steps, warmup):
-    """(ms per step, stage timings) of fn() on the current stream."""
-    import torch
-
-    import paper_1710_08037_amd as plv
-
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
-    plv.timing_enable(True)
-    plv.timing_read(reset=True)
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    start.record()
-    for _ in range(steps):
-        fn()
-    stop.record()
-    torch.cuda.synchronize()
-    stages = plv.timing_read(reset=True)
-    plv.timing_enable(False)
+    """(median ms per step, stage ms per step) of fn() on the current stream."""
+    med, mean, stages, _ = step_times(fn, steps, warmup)
     per = {k: round(v[0] / steps, 4) for k, v in stages.items() if v[1]}
-    return start.elapsed_time(stop) / steps, per
+    per["mean_ms_per_step"] = round(mean, 4)
+    return med, per
 
 
 def line_for(workload, value, ms, args, dtype, config, extra):
@@ -204,7 +265,7 @@ def bench_small(args):
     ms, stages = timed(lambda: plv.from_real(x, 256.0, prec="f64"), args.steps, args.warmup)
     ps = 64 * 63 // 2 * 2048
     return line_for("small FP64: N=64 real f64 x T=2048 at 256 Hz, plain analytic signal", ps / (ms / 1e3), ms,
-                    args, "f64", {"n": 64, "t": 2048, "prec": "f64"}, {"stage_ms": stages})
+                    args, DTYPE["f64"], {"n": 64, "t": 2048, "prec": "f64"}, {"stage_ms": stages})
 
 
 def bench_batch(args):
@@ -223,7 +284,7 @@ def bench_batch(args):
                        args.warmup)
     ps = sum(n * (n - 1) // 2 * t for n, t in shapes) * len(bands)
     return line_for("uneven batch: 512 trials, N in {68,148,360,1000}, T in [500,4000], 5 bands, real f32",
-                    ps / (ms / 1e3), ms, args, "bf16", {"trials": 512, "bands": len(bands),
+                    ps / (ms / 1e3), ms, args, DTYPE[args.prec_batch], {"trials": 512, "bands": len(bands),
                                                         "prec": args.prec_batch},
                     {"stage_ms": stages, "pair_samples": ps, "rows": sum(n for n, _ in shapes)})
 
@@ -249,7 +310,7 @@ def bench_grad(args):
     ms, stages = timed(step, args.steps, args.warmup)
     ps = n * (n - 1) // 2 * t
     return line_for("differentiable ciPLV: N=2048 real f32 x T=8192, forward + adjoint", ps / (ms / 1e3), ms,
-                    args, "bf16", {"n": n, "t": t, "prec": args.prec_batch}, {"stage_ms": stages})
+                    args, DTYPE[args.prec_batch], {"n": n, "t": t, "prec": args.prec_batch}, {"stage_ms": stages})
 
 
 def bench_fir(args):
@@ -274,7 +335,7 @@ def bench_fir(args):
         extra["gram_frac_of_peak"] = round(flops / (stages["gram"] / 1e3) / 1e12 / PEAK_TFLOPS[prec], 4)
     return line_for("FIR band-pass then PLV: N=2048 real f32 x T=8192 at 1 kHz (4096-sample epoch, 2048 "
                     "samples of padding each side), 8-12 Hz FIR of order 2000 applied forward and backward",
-                    ps / (ms / 1e3), ms, args, "bf16", {"n": n, "t": t, "window": list(win), "fir_order": order,
+                    ps / (ms / 1e3), ms, args, DTYPE[prec], {"n": n, "t": t, "window": list(win), "fir_order": order,
                                                        "prec": prec}, extra)
 
 
@@ -299,7 +360,7 @@ def bench_coherence(args):
         extra["gram_issued_frac_of_peak"] = round(issued_flops(prec, n, t) / (stages["gram"] / 1e3) / 1e12
                                                   / PEAK_TFLOPS[prec], 4)
     return line_for("coherency: N=1024 complex coefficient rows x T=60000, amplitude-modulated mixtures",
-                    ps / (ms / 1e3), ms, args, "bf16", {"n": n, "t": t, "prec": prec}, extra)
+                    ps / (ms / 1e3), ms, args, DTYPE[prec], {"n": n, "t": t, "prec": prec}, extra)
 
 
 def bench_trials(args):
@@ -319,7 +380,7 @@ def bench_trials(args):
     ms, stages = timed(lambda: plv.over_trials(z, prec=prec), args.steps, args.warmup)
     ps = n * (n - 1) // 2 * ntr * t
     return line_for("PLV across trials: 148 signals x 40 trials x 4000 time points, complex64",
-                    ps / (ms / 1e3), ms, args, "bf16", {"n": n, "trials": ntr, "t": t, "prec": prec},
+                    ps / (ms / 1e3), ms, args, DTYPE[prec], {"n": n, "trials": ntr, "t": t, "prec": prec},
                     {"stage_ms": stages, "matrices_per_s": round(t / (ms / 1e3), 1)})
 
 
@@ -358,7 +419,7 @@ def bench_brain(args):
         extra["cpu_baseline"], extra["max_abs_err"] = brain_cpu_leg(z, pairs, box["out"])
     extra["steps_note"] = "at most 3 timed steps of about a second each"
     line = line_for("whole-brain: N=15000 unit phasors x T=1.2e6 (complex64, generated on the GPU), "
-                    "200 planted lagged pairs", ps / (ms / 1e3), ms, args, prec, {"n": n, "t": t, "prec": prec},
+                    "200 planted lagged pairs", ps / (ms / 1e3), ms, args, DTYPE[prec], {"n": n, "t": t, "prec": prec},
                     extra)
     line["steps"] = steps
     line["warmup"] = warm
@@ -462,8 +523,8 @@ def main():
     results = {}
     precs = ("split_bf16", "f32") if args.prec == "both" else (args.prec,)
     for prec in precs:
-        ms, stages = run_gpu(z, prec, args.steps, args.warmup)
-        results[prec] = {"ms": ms, "stages": stages}
+        ms, mean, stages, gram = run_gpu(z, prec, args.steps, args.warmup)
+        results[prec] = {"ms": ms, "mean": mean, "stages": stages, "gram": gram}
     if args.prec == "f32":
         print(json.dumps({"f32_ms_per_step": results["f32"]["ms"]}), flush=True)
         return
@@ -482,12 +543,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": DTYPE[main_prec],
         "data": "synthetic",
         "config": {"workload": "sensor-scale analytic PLV: N=1024 complex64 signals x T=60000 samples, "
                                "lagged oscillators (32 latents, 8-12 Hz), split-BF16 Gram",
                    "n": N_SIG, "t": T_SAMP, "prec": main_prec},
-        "roofline": roofline(main_prec, N_SIG, T_SAMP, results[main_prec]["stages"]),
+        "roofline": roofline(main_prec, N_SIG, T_SAMP, results[main_prec]["stages"], results[main_prec]["gram"]),
+        "mean_ms_per_step": round(results[main_prec]["mean"], 4),
+        "timing": "median of per-step HIP event pairs on the launch stream; kernel_ms the median per launch",
     }
     stage_ms = {}
     for prec, r in results.items():
@@ -495,7 +558,8 @@ def main():
     if "f32" in results:
         line["fp32"] = {"value": round(pair_samples / (results["f32"]["ms"] / 1e3), 1), "ms_per_step":
                         round(results["f32"]["ms"], 4), "roofline": roofline("f32", N_SIG, T_SAMP,
-                                                                              results["f32"]["stages"])}
+                                                                              results["f32"]["stages"],
+                                                                              results["f32"]["gram"])}
         line["split_vs_fp32_speedup"] = round(results["f32"]["ms"] / ms, 3)
     line["stage_ms"] = stage_ms
     if not args.no_cpu:

@@ -182,6 +182,15 @@ plv_status plv_timing_enable(plv_ctx *ctx, int32_t on);
 /* Wait for the recorded events, add up their times into *out (host) and, if
  * reset != 0, forget them. */
 plv_status plv_timing_read(plv_ctx *ctx, plv_timing *out, int32_t reset);
+/* Per-call times of one stage: waits for the recorded (not yet reset) events
+ * of `stage` and writes the duration of each recorded stage execution, in
+ * call order, to ms[0..cap) (host, milliseconds) and its kernel launch count
+ * to launches[0..cap) (host, may be NULL).  *count (host) receives the number
+ * of recorded executions of the stage, which may exceed cap.  Nothing is
+ * forgotten.  PLV_ERR_INVALID_ARG for a stage outside [0, PLV_NSTAGES), a
+ * negative cap, or ms == NULL with cap > 0. */
+plv_status plv_timing_list(plv_ctx *ctx, int32_t stage, double *ms, int32_t *launches, int64_t cap,
+                           int64_t *count);
 
 /* ------------------------------------------------------------- workspace */
 

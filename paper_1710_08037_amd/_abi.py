@@ -38,7 +38,7 @@ class Grad(C.Structure):
 
 # every symbol include/plv.h declares
 EXPORTS = ("plv_create", "plv_destroy", "plv_status_str", "plv_last_error", "plv_version",
-           "plv_timing_enable", "plv_timing_read",
+           "plv_timing_enable", "plv_timing_read", "plv_timing_list",
            "plv_workspace_size", "plv_from_analytic", "plv_from_real", "plv_coherence",
            "plv_trials_workspace_size", "plv_over_trials", "plv_backward", "plv_autotune")
 
@@ -82,6 +82,9 @@ def lib():
             L.plv_timing_enable.restype = C.c_int
             L.plv_timing_read.argtypes = [P, C.POINTER(Timing), C.c_int32]
             L.plv_timing_read.restype = C.c_int
+            L.plv_timing_list.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_int64,
+                                          C.POINTER(C.c_int64)]
+            L.plv_timing_list.restype = C.c_int
             L.plv_workspace_size.argtypes = [P, C.c_int, C.c_int, C.POINTER(Problem), C.c_int64, C.POINTER(Band),
                                              C.c_int32, C.POINTER(C.c_size_t)]
             L.plv_workspace_size.restype = C.c_int

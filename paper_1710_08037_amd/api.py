@@ -259,6 +259,20 @@ def timing_read(reset=True, device=None):
     return {name: (t.ms[k], t.calls[k], t.launches[k]) for k, name in enumerate(_abi.STAGES)}
 
 
+def timing_list(stage, device=None):
+    """[(ms, launches)] of every recorded execution of `stage` (a name from
+    timing_read's keys), in call order, without resetting."""
+    ctx = context(device)
+    k = _abi.STAGES.index(stage)
+    cnt = C.c_int64(0)
+    _abi.check(_abi.lib().plv_timing_list(ctx.handle, k, None, None, 0, C.byref(cnt)), ctx.handle)
+    n = cnt.value
+    ms = (C.c_double * max(n, 1))()
+    ln = (C.c_int32 * max(n, 1))()
+    _abi.check(_abi.lib().plv_timing_list(ctx.handle, k, ms, ln, n, C.byref(cnt)), ctx.handle)
+    return [(ms[i], ln[i]) for i in range(n)]
+
+
 def backward_batch(xs, gs, upstream, fs=None, bands=None, prec="split_bf16", windows=None):
     """dL/d(input) for each problem through plv_backward.
 

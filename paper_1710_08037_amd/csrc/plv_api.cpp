@@ -172,7 +172,33 @@ plv_status plv_timing_read(plv_ctx *ctx, plv_timing *out, int32_t reset)
     return PLV_OK;
 }
 
-int32_t plv_version(void) { return 10000; }
+plv_status plv_timing_list(plv_ctx *ctx, int32_t stage, double *ms, int32_t *launches, int64_t cap,
+                           int64_t *count)
+{
+    if (!ctx || !count || stage < 0 || stage >= PLV_NSTAGES || cap < 0 || (cap > 0 && !ms))
+        return PLV_ERR_INVALID_ARG;
+    int64_t k = 0;
+    for (const TimingRec &r : ctx->recs) {
+        if (r.stage != stage)
+            continue;
+        if (k < cap) {
+            float v = 0.0f;
+            hipError_t e = hipEventSynchronize(r.stop);
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&v, r.start, r.stop);
+            if (e != hipSuccess)
+                return hip_fail(ctx, e, "reading stage timing events");
+            ms[k] = v;
+            if (launches)
+                launches[k] = r.launches;
+        }
+        ++k;
+    }
+    *count = k;
+    return PLV_OK;
+}
+
+int32_t plv_version(void) { return 10100; }
 
 const char *plv_status_str(plv_status s)
 {
