@@ -447,10 +447,8 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
     if (d.ub) {  // general product: full grid, row-major over (I, J)
         I = tile / d.ntile_b;
         J = tile - I * d.ntile_b;
-    } else if (args.order) {  // blocked launch order of a single problem
-        const int v = args.order[tile];
-        I = v >> 16;
-        J = v & 0xffff;
+    } else if (args.blocked) {  // blocked launch order of a single problem
+        blocked_tile(tile, d.ntile, I, J);
     } else {
         tile_ij(tile, d.ntile, I, J);
     }

@@ -518,17 +518,9 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
     std::vector<int> class_start, class_count;  // FFT rows per size class
     bool any_direct = false;                    // some band synthesised from its bins
     int64_t synth_jobs = 0;                     // its work-groups
-    if (plan.grouped || real || plan.has_order) {
+    if (plan.grouped || real) {
         std::vector<uint8_t> blob(plan.tables_bytes, 0);
         memcpy(blob.data() + plan.desc_off, gd.data(), gd.size() * sizeof(GramDesc));
-        if (plan.has_order) {
-            std::vector<int32_t> order;
-            blocked_order(gd[0].ntile, order);
-            if ((int)order.size() != gd[0].nupper)
-                return fail(ctx, PLV_ERR_UNSUPPORTED, "internal: tile order has %zu entries for %d tiles", order.size(),
-                            gd[0].nupper);
-            memcpy(blob.data() + plan.order_off, order.data(), order.size() * sizeof(int32_t));
-        }
         if (plan.grouped) {
             memcpy(blob.data() + plan.item_off, items.data(), items.size() * sizeof(Item));
             memcpy(blob.data() + plan.tile_off, tiles.data(), tiles.size() * sizeof(TileRef));
@@ -647,7 +639,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
                 HerkArgs ha{};
                 ha.g = d;
                 ha.pass = p;
-                ha.order = plan.has_order ? (const int32_t *)(ws + plan.order_off) : nullptr;
+                ha.blocked = plan.blocked ? 1 : 0;
                 const int nch = std::min(d.nslot, d.nchunk - p * d.nslot);
                 if ((e = launch_herk(mode, ha, d.nupper * nch, s)) != hipSuccess)
                     return hip_fail(ctx, e, "gram kernel launch");

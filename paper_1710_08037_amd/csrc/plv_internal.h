@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include "plv.h"
+#include "tile_order.h"
 
 #define PLV_KGRAN 32  // sample granule of tpad and of every K-chunk
 
@@ -117,7 +118,7 @@ struct HerkArgs {
     const Item *items;      // work items (grouped launch: `chunk` is the slot; gram < 0: none), or nullptr
     int32_t nitems;
     int32_t pass;           // chunk = pass * nslot + slot; pass > 0 adds into the slot
-    const int32_t *order;   // single Gram problem: tile position -> I << 16 | J, or nullptr
+    int32_t blocked;        // single Gram problem: tiles in the blocked order (tile_order.h)
 };
 
 struct EpiArgs {

@@ -315,9 +315,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         }
         choose_chunks_single(plan.grams[0], slots, bm, MAX_CHUNK, forced);
         plan.grams[0].fused = plan.grams[0].nchunk == 1 && op != PLV_OP_COHERENCE;
-        plan.has_order = true;
-        plan.order_off = off;
-        off += align256((size_t)plan.grams[0].nupper * sizeof(int32_t));
+        plan.blocked = true;
     }
     if (real) {
         const int maxlog = mode == M_F64 ? FFT_MAXLOG_F64 : FFT_MAXLOG_F32;
@@ -505,23 +503,6 @@ void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd)
         }
         gd.push_back(d);
     }
-}
-
-// Tiles that run at the same time on one XCD (consecutive items) form a
-// compact block, so they share ORDER_BR row panels and ORDER_BC column
-// panels in that XCD's L2 instead of one row panel and a column panel each.
-void blocked_order(int ntile, std::vector<int32_t> &order)
-{
-    order.clear();
-    for (int bi = 0; bi * ORDER_BR < ntile; ++bi)
-        for (int bj = 0; bj * ORDER_BC < ntile; ++bj) {
-            if (bj * ORDER_BC + ORDER_BC - 1 < bi * ORDER_BR)
-                continue;  // wholly below the diagonal
-            for (int i = bi * ORDER_BR; i < std::min(ntile, (bi + 1) * ORDER_BR); ++i)
-                for (int j = bj * ORDER_BC; j < std::min(ntile, (bj + 1) * ORDER_BC); ++j)
-                    if (i <= j)
-                        order.push_back((int32_t)(i << 16 | j));
-        }
 }
 
 void build_tables(const Plan &plan, const std::vector<GramDesc> &gd, std::vector<Item> &items,

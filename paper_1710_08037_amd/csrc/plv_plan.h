@@ -60,8 +60,7 @@ struct Plan {
     std::vector<GramPlan> grams;
     size_t tables_off = 0, tables_bytes = 0;  // device tables, uploaded once per call
     size_t desc_off = 0, item_off = 0, tile_off = 0;
-    size_t order_off = 0;                     // single Gram problem: blocked tile order
-    bool has_order = false;
+    bool blocked = false;                     // single Gram problem: blocked tile order (tile_order.h)
     size_t nitems = 0, ntiles = 0;
     std::vector<Item> items;                  // grouped launch: work items, XCD-major (see schedule_items)
     bool grouped = false;                     // Gram work from the item table
@@ -96,11 +95,6 @@ void chunk_counts(const Plan &plan, std::vector<int> &out);
 std::tuple<int, int64_t, int64_t> tune_key(const Plan &plan);
 
 void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd);
-// Launch order of the upper-triangle tiles of an ntile x ntile grid: blocks
-// of ORDER_BR x ORDER_BC tiles, row-major over blocks and within a block,
-// each entry I << 16 | J.
-constexpr int ORDER_BR = 4, ORDER_BC = 8;
-void blocked_order(int ntile, std::vector<int32_t> &order);
 void build_tables(const Plan &plan, const std::vector<GramDesc> &gd, std::vector<Item> &items,
                   std::vector<TileRef> &tiles);
 
