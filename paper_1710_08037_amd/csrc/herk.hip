@@ -448,7 +448,11 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
         I = tile / d.ntile_b;
         J = tile - I * d.ntile_b;
     } else if (args.blocked) {  // blocked launch order of a single problem
-        blocked_tile(tile, d.ntile, I, J);
+        // The position comes out of a VALU division: move it to a scalar
+        // register first.  Decoded from a vector register, the decode's last
+        // loop was compiled with a select on a stale SCC that never lowered
+        // the position, so the work-group never left it.
+        blocked_tile(__builtin_amdgcn_readfirstlane(tile), __builtin_amdgcn_readfirstlane(d.ntile), I, J);
     } else {
         tile_ij(tile, d.ntile, I, J);
     }
