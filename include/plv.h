@@ -221,6 +221,30 @@ plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, 
                          const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes,
                          void *stream);
 
+/* Allocation-free variant of plv_from_analytic, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same computation, arguments and outputs
+ * as plv_from_analytic with nprob = 1, but with no workspace argument: the
+ * intermediate buffers (phasor planes, FP64 chunk partial sums) live in a
+ * device array of PLV_NOALLOC_MAX_BYTES inside the library, one per GPU,
+ * held until the process ends (its address on each device is looked up once,
+ * in plv_create).  The call makes no hipMalloc / hipFree or other allocating
+ * call and no host-to-device copy.  The caller still allocates and owns the
+ * input and the outputs.
+ *   Errors: PLV_ERR_UNSUPPORTED when nprob != 1 or when the problem needs more
+ *   than PLV_NOALLOC_MAX_BYTES of scratch (the message gives the size needed;
+ *   plv_workspace_size with PLV_OP_FROM_ANALYTIC returns the same figure);
+ *   PLV_ERR_DEVICE when the library could not find its scratch array on this
+ *   device; otherwise as plv_from_analytic.
+ *   Concurrency: every call on one GPU uses that GPU's single scratch array,
+ *   and the array keeps the previous call's contents (nothing in it needs to
+ *   start at zero).  Calls on one stream are ordered and safe; calls whose
+ *   work can overlap on one GPU (different streams, other host threads, other
+ *   contexts on the same device) race on the array and give wrong results. */
+#define PLV_NOALLOC_MAX_BYTES (64u << 20) /* 64 MiB per GPU */
+plv_status plv_from_analytic_noalloc(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                                     void *stream);
+
 /* Coherency of complex rows (Section II.B, Eq. 12): Fourier coefficients of
  * one frequency over trials or windows, or analytic signals over time, given
  * exactly as for plv_from_analytic (interleaved c64; c128 for PLV_PREC_F64).

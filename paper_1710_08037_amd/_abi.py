@@ -13,6 +13,7 @@ STATUS = {0: "PLV_OK", 1: "PLV_ERR_INVALID_ARG", 2: "PLV_ERR_WORKSPACE", 3: "PLV
 PREC = {"f64": 0, "f32": 1, "split_bf16": 2, "bf16": 3, "f16": 4}
 INPUT_ANALYTIC, INPUT_REAL = 0, 1
 OP_FROM_ANALYTIC, OP_FROM_REAL, OP_BACKWARD_ANALYTIC, OP_BACKWARD_REAL, OP_COHERENCE = 0, 1, 2, 3, 4
+NOALLOC_MAX_BYTES = 64 << 20  # PLV_NOALLOC_MAX_BYTES
 
 
 class Problem(C.Structure):
@@ -39,7 +40,7 @@ class Grad(C.Structure):
 # every symbol include/plv.h declares
 EXPORTS = ("plv_create", "plv_destroy", "plv_status_str", "plv_last_error", "plv_version",
            "plv_timing_enable", "plv_timing_read", "plv_timing_list",
-           "plv_workspace_size", "plv_from_analytic", "plv_from_real", "plv_coherence",
+           "plv_workspace_size", "plv_from_analytic", "plv_from_analytic_noalloc", "plv_from_real", "plv_coherence",
            "plv_trials_workspace_size", "plv_over_trials", "plv_backward", "plv_autotune")
 
 STAGES = ("hilbert", "normalise", "gram", "epilogue", "backward")
@@ -90,6 +91,8 @@ def lib():
             L.plv_workspace_size.restype = C.c_int
             L.plv_from_analytic.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64, P, C.c_size_t, P]
             L.plv_from_analytic.restype = C.c_int
+            L.plv_from_analytic_noalloc.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64, P]
+            L.plv_from_analytic_noalloc.restype = C.c_int
             L.plv_coherence.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64, P, C.c_size_t, P]
             L.plv_coherence.restype = C.c_int
             L.plv_trials_workspace_size.argtypes = [P, C.c_int, C.POINTER(Trials), C.POINTER(C.c_size_t)]

@@ -93,6 +93,24 @@ def _workspace(ctx, op, prec, probs, bands, nb, dev):
 ALL = ("plv", "iplv", "ciplv")
 
 
+def from_analytic_noalloc(z, prec="split_bf16", window=None, want=ALL, want_g=False):
+    """from_analytic for one problem through plv_from_analytic_noalloc: no
+    workspace, the library's per-device scratch array instead (problems whose
+    intermediate buffers exceed its size are rejected).  The outputs are still
+    allocated here, by torch."""
+    p = _prec_id(prec)
+    dev = z.device
+    cd = torch.complex128 if p == 0 else torch.complex64
+    rd = torch.float64 if p == 0 else torch.float32
+    if z.dtype != cd:
+        raise TypeError("prec %s needs %s input, got %s" % (prec, cd, z.dtype))
+    o = _outputs(z.shape[0], 1, rd, cd, dev, want, want_g)
+    arr = _abi.problems([_problem(z, window, o)])
+    ctx = context(dev)
+    _abi.check(_abi.lib().plv_from_analytic_noalloc(ctx.handle, p, arr, 1, _stream(dev)), ctx.handle)
+    return {k: (v[0] if v is not None else None) for k, v in o.items()}
+
+
 def from_analytic_batch(zs, prec="split_bf16", windows=None, want=ALL, want_g=False):
     """PLV/iPLV/ciPLV of several analytic-signal problems in one grouped call.
 

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -19,6 +20,20 @@
 #include "plv_plan.h"
 
 using namespace plv;
+
+// Device scratch of plv_from_analytic_noalloc: one copy of this array per
+// GPU the library runs on, held until the process ends.  Host code never
+// uses its name as an address (that is a host-side stand-in); the device
+// address of each GPU's copy is looked up once per device, in plv_create
+// with that device current, and kept in scratch_ptr.
+static __device__ __align__(256) uint8_t scratch[PLV_NOALLOC_MAX_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES];          // device address of each device's copy, or nullptr
+hipError_t scratch_err[MAX_DEVICES];     // the lookup's result when it failed
+}  // namespace
 
 struct TimingRec {
     int stage;
@@ -39,6 +54,8 @@ struct plv_ctx {
     std::vector<TimingRec> recs;   // recorded, not yet read
     std::vector<hipEvent_t> pool;  // idle events
     plv::TuneMap tune;             // measured K-chunk counts (plv_autotune)
+    void *scratch = nullptr;       // this device's copy of `scratch` (plv_from_analytic_noalloc)
+    hipError_t scratch_err = hipSuccess;
 };
 
 namespace {
@@ -239,6 +256,20 @@ plv_status plv_create(plv_ctx **out, int device)
             ctx->cus = cus;
         for (int m = 0; m < 5; ++m)
             ctx->occ[m] = herk_occupancy(m);
+        if (device < MAX_DEVICES) {
+            // once per device, with the device current: its copy of the scratch array
+            std::lock_guard<std::mutex> lk(scratch_mu);
+            if (!scratch_ptr[device] && scratch_err[device] == hipSuccess) {
+                void *p = nullptr;
+                const hipError_t se = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+                if (se == hipSuccess && p)
+                    scratch_ptr[device] = p;
+                else
+                    scratch_err[device] = se != hipSuccess ? se : hipErrorInvalidSymbol;
+            }
+            ctx->scratch = scratch_ptr[device];
+            ctx->scratch_err = scratch_err[device];
+        }
         e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming);
         (void)hipSetDevice(cur);
         if (e != hipSuccess) {
@@ -699,6 +730,43 @@ plv_status plv_from_analytic(plv_ctx *ctx, plv_prec prec, const plv_problem *pro
     if (st != PLV_OK)
         return st;
     return enqueue_forward(ctx, plan, probs, nullptr, 1, 0.0, (uint8_t *)ws, (hipStream_t)stream);
+}
+
+plv_status plv_from_analytic_noalloc(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                                     void *stream)
+{
+    if (!ctx)
+        return PLV_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (ctx->device < 0)
+        return fail(ctx, PLV_ERR_INVALID_ARG, "host-only context cannot compute");
+    if (nprob != 1)
+        return fail(ctx, PLV_ERR_UNSUPPORTED, "the allocation-free entry point takes exactly one problem (nprob = %lld)",
+                    (long long)nprob);
+    if (!ctx->scratch)
+        return fail(ctx, PLV_ERR_DEVICE, "device scratch address not available: %s",
+                    ctx->device >= MAX_DEVICES ? "device index beyond the library's table"
+                                               : hipGetErrorString(ctx->scratch_err));
+    Plan plan;
+    std::string why;
+    plv_status st = make_plan(ctx->cus, ctx->occ, PLV_OP_FROM_ANALYTIC, prec, probs, 1, nullptr, 1, plan, why,
+                              &ctx->tune);
+    if (st != PLV_OK)
+        return fail(ctx, st, "%s", why.c_str());
+    if (plan.total > (size_t)PLV_NOALLOC_MAX_BYTES)
+        return fail(ctx, PLV_ERR_UNSUPPORTED,
+                    "problem needs %zu bytes of scratch; the allocation-free entry point has %zu (use plv_from_analytic "
+                    "with a workspace)",
+                    plan.total, (size_t)PLV_NOALLOC_MAX_BYTES);
+    if (plan.grouped)
+        return fail(ctx, PLV_ERR_UNSUPPORTED, "internal: a single problem planned as a grouped launch");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "hipSetDevice");
+    // a single analytic problem uploads no tables (its descriptor travels as
+    // a kernel argument and its tile order is decoded on the device), so the
+    // call below makes no allocation and no host-to-device copy
+    return enqueue_forward(ctx, plan, probs, nullptr, 1, 0.0, (uint8_t *)ctx->scratch, (hipStream_t)stream);
 }
 
 // Across trials: one Gram problem per time point (rows = signals, samples =
