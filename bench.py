@@ -111,11 +111,12 @@ def measured_traffic(kernel, workload):
     return None
 
 
-def issued_flops(prec, n, t):
+def issued_flops(prec, n, t, bm=None):
     """MFMA work the Gram kernel issues: whole BM x BM tiles of the upper
     triangle (diagonal tiles in full, rows padded to the tile) over K padded
-    to 32 samples."""
-    bm = 64 if prec == "f64" else 128
+    to 32 samples.  bm: the tile edge (default: the largest of the mode)."""
+    if bm is None:
+        bm = 64 if prec == "f64" else 128
     ntile = -(-n // bm)
     return FLOP_PER_PAIR_SAMPLE[prec] * (ntile * (ntile + 1) // 2) * bm * bm * (-(-t // 32) * 32)
 
@@ -280,13 +281,22 @@ def bench_batch(args):
     xs = [torch.from_numpy(synth.glag_real(n, t, 1000.0, 32, (2.0, 42.0), seed=seed + 1 + k,
                                            dtype=np.float32)).cuda() for k, (n, t) in enumerate(shapes)]
     bands = synth.bands_hz()
+    if args.autotune:
+        plv.autotune_batch(xs, prec=args.prec_batch, fs=1000.0, bands=bands)
     ms, stages = timed(lambda: plv.from_real_batch(xs, 1000.0, bands=bands, prec=args.prec_batch), args.steps,
                        args.warmup)
     ps = sum(n * (n - 1) // 2 * t for n, t in shapes) * len(bands)
+    edges = {n: plv.tile_edge(n, args.prec_batch) for n in sorted({n for n, _ in shapes})}
+    issued = sum(issued_flops(args.prec_batch, n, t, edges[n]) for n, t in shapes) * len(bands)
+    useful = FLOP_PER_PAIR_SAMPLE[args.prec_batch] * ps
     return line_for("uneven batch: 512 trials, N in {68,148,360,1000}, T in [500,4000], 5 bands, real f32",
                     ps / (ms / 1e3), ms, args, DTYPE[args.prec_batch], {"trials": 512, "bands": len(bands),
                                                         "prec": args.prec_batch},
-                    {"stage_ms": stages, "pair_samples": ps, "rows": sum(n for n, _ in shapes)})
+                    {"stage_ms": stages, "pair_samples": ps, "rows": sum(n for n, _ in shapes),
+                     "tile_edges": {str(k): v for k, v in edges.items()}, "autotuned": bool(args.autotune),
+                     "issued_over_useful_mfma": round(issued / useful, 4),
+                     "gram_frac_of_peak": round(useful / (stages["gram"] / 1e3) / 1e12
+                                                / PEAK_TFLOPS[args.prec_batch], 4) if stages.get("gram") else None})
 
 
 def bench_grad(args):
@@ -492,6 +502,8 @@ def main():
                     help="only run a plain device copy of BYTES bytes 3 times (counter calibration) and exit")
     ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain", "coherence", "trials", "fir"])
     ap.add_argument("--prec-batch", default="split_bf16", help="precision of the batch and grad workloads")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batch workload: measure the tile edge per row count (plv_autotune) before timing")
     ap.add_argument("--prec-brain", default="bf16", choices=["bf16", "f16"], help="precision of the brain workload")
     args = ap.parse_args()
     if args.gpus != 1:

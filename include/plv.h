@@ -294,29 +294,47 @@ plv_status plv_over_trials(plv_ctx *ctx, plv_prec prec, const plv_trials *p, voi
 
 /* -------------------------------------------------------------- autotune */
 
-/* Measure the K-chunk count of a single-problem forward call (one problem, one
- * band) on this device and keep the fastest in `ctx`.  The Gram sums over T
- * (Eqs. 6-7) run as K-chunks, one work-group per (tile, chunk); the planner
- * picks their number from a cost model, and this call replaces that choice by
- * a measurement: the model's count and up to two exact splits on either side
- * are each run once untimed and three times between HIP events on `stream`
- * (the outputs are written as by the call itself); a count must beat the best
- * so far by more than 1% to replace it.  Every later plan on `ctx` with the
- * same precision, row count and padded length (plv_workspace_size included:
- * query it again, the partial-sum slots depend on the count) uses the winner.
+/* Measure the launch shape of a forward call on this device and keep the
+ * fastest in `ctx`.  Not part of the paper: a tuning aid for the launch.
+ *   One problem and one band: the K-chunk count.  The Gram sums over T
+ *   (Eqs. 6-7) run as K-chunks, one work-group per (tile, chunk); the planner
+ *   picks their number from a cost model, and this call replaces that choice
+ *   by a measurement of the model's count and up to two exact splits on
+ *   either side.  Every later plan on `ctx` with the same precision, row
+ *   count and padded length uses the winner.
+ *   Several problems or bands (one grouped launch, e.g. trials x bands of
+ *   uneven size): the tile edge of each distinct row count n.  The Gram
+ *   kernel has 128- and 64-wide output tiles (64 only in PLV_PREC_F64); for
+ *   every n among the problems the call is run on the problems with that n
+ *   alone, once per edge, and the faster edge is kept for row count n in
+ *   every later forward plan on `ctx` (plv_tile_edge reports it).
+ * Each candidate is run once untimed and three times between HIP events on
+ * `stream` (the outputs are written as by the call itself); a candidate must
+ * beat the best so far by more than 1% to replace it.  Query
+ * plv_workspace_size again afterwards: the workspace depends on the choices.
  *   op: PLV_OP_FROM_ANALYTIC, PLV_OP_FROM_REAL or PLV_OP_COHERENCE; the other
  *     arguments exactly as for that call (bands/nbands/fs are read for
- *     PLV_OP_FROM_REAL only).  Counts whose workspace exceeds ws_bytes are
+ *     PLV_OP_FROM_REAL only).  Candidates whose workspace exceeds ws_bytes are
  *     skipped.
- *   nchunk (host, may be NULL): the count kept, or 0 when there is nothing to
- *     choose (several problems or bands: a grouped launch gives every chunk
- *     its own slot).
+ *   nchunk (host, may be NULL): the chunk count kept for a single problem, or
+ *     0 for a grouped call.
  * Blocks the host until the trial runs have finished.  Argument errors as for
  * the compute call; PLV_ERR_DEVICE on a failed launch or event (the previous
- * choice is then kept).  Not part of the paper: a tuning aid for the launch. */
+ * choice is then kept). */
 plv_status plv_autotune(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
                         const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes, void *stream,
                         int32_t *nchunk);
+
+/* Tile edge (64 or 128) that a forward problem of n rows gets on `ctx` in
+ * precision `prec`: the one plv_autotune measured or plv_set_tile_edge set,
+ * else the planner's model (the edge with the smaller whole-tile MFMA work
+ * over the upper triangle, the 64-wide tile's work weighted by 1/0.85).
+ * ctx may be a host-only context or NULL (model only).  *bm is host. */
+plv_status plv_tile_edge(const plv_ctx *ctx, plv_prec prec, int64_t n, int32_t *bm);
+/* Set the tile edge of forward problems with n rows on `ctx` (bm = 64 or 128;
+ * 64 only in PLV_PREC_F64), or return them to the model (bm = 0).  Host-only
+ * bookkeeping; query plv_workspace_size afterwards. */
+plv_status plv_set_tile_edge(plv_ctx *ctx, plv_prec prec, int64_t n, int32_t bm);
 
 /* -------------------------------------------------------------- backward */
 

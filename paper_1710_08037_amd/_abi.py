@@ -41,7 +41,8 @@ class Grad(C.Structure):
 EXPORTS = ("plv_create", "plv_destroy", "plv_status_str", "plv_last_error", "plv_version",
            "plv_timing_enable", "plv_timing_read", "plv_timing_list",
            "plv_workspace_size", "plv_from_analytic", "plv_from_analytic_noalloc", "plv_from_real", "plv_coherence",
-           "plv_trials_workspace_size", "plv_over_trials", "plv_backward", "plv_autotune")
+           "plv_trials_workspace_size", "plv_over_trials", "plv_backward", "plv_autotune",
+           "plv_tile_edge", "plv_set_tile_edge")
 
 STAGES = ("hilbert", "normalise", "gram", "epilogue", "backward")
 NSTAGES = 8
@@ -108,6 +109,10 @@ def lib():
             L.plv_autotune.argtypes = [P, C.c_int, C.c_int, C.POINTER(Problem), C.c_int64, C.POINTER(Band), C.c_int32,
                                        C.c_double, P, C.c_size_t, P, C.POINTER(C.c_int32)]
             L.plv_autotune.restype = C.c_int
+            L.plv_tile_edge.argtypes = [P, C.c_int, C.c_int64, C.POINTER(C.c_int32)]
+            L.plv_tile_edge.restype = C.c_int
+            L.plv_set_tile_edge.argtypes = [P, C.c_int, C.c_int64, C.c_int32]
+            L.plv_set_tile_edge.restype = C.c_int
             _LIB = L
     return _LIB
 

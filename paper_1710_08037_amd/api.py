@@ -263,6 +263,50 @@ def autotune(x, prec="split_bf16", window=None, fs=None, bands=None, coherence=F
     return chosen.value
 
 
+def autotune_batch(xs, prec="split_bf16", fs=None, bands=None, windows=None, coherence=False):
+    """Measure the tile edge of every distinct row count of a grouped forward
+    call (several problems, or real rows with several bands) through
+    plv_autotune, and keep the choices for later calls on this device.
+
+    xs: the call's inputs, as for from_analytic_batch / from_real_batch /
+    coherence_batch.  Returns {n: tile edge} for the row counts of xs.
+    Blocks until the trial runs finish.
+    """
+    p = _prec_id(prec)
+    dev = xs[0].device
+    real = not xs[0].is_complex()
+    barr, nb = _abi.bands(bands) if real else (None, 1)
+    rd = torch.float64 if p == 0 else torch.float32
+    cd = torch.complex128 if p == 0 else torch.complex64
+    outs, probs = [], []
+    for k, x in enumerate(xs):
+        o = _outputs(x.shape[0], nb, rd, cd, dev, ALL, False)
+        outs.append(o)
+        probs.append(_problem(x, None if windows is None else windows[k], o))
+    arr = _abi.problems(probs)
+    op = _abi.OP_FROM_REAL if real else (_abi.OP_COHERENCE if coherence else _abi.OP_FROM_ANALYTIC)
+    ctx = context(dev)
+    ws = _workspace(ctx, op, p, arr, barr, nb, dev)
+    _abi.check(_abi.lib().plv_autotune(ctx.handle, op, p, arr, len(probs), barr, nb, float(fs or 0.0),
+                                       C.c_void_p(ws.data_ptr()), ws.numel(), _stream(dev), None), ctx.handle)
+    return {int(x.shape[0]): tile_edge(int(x.shape[0]), prec, dev) for x in xs}
+
+
+def tile_edge(n, prec="split_bf16", device=None):
+    """Tile edge (64 or 128) of a forward problem of n rows on this device."""
+    ctx = context(device)
+    bm = C.c_int32(0)
+    _abi.check(_abi.lib().plv_tile_edge(ctx.handle, _prec_id(prec), int(n), C.byref(bm)), ctx.handle)
+    return bm.value
+
+
+def set_tile_edge(n, bm, prec="split_bf16", device=None):
+    """Force the tile edge of forward problems of n rows (bm 64 or 128), or
+    return them to the planner's model (bm = 0)."""
+    ctx = context(device)
+    _abi.check(_abi.lib().plv_set_tile_edge(ctx.handle, _prec_id(prec), int(n), int(bm)), ctx.handle)
+
+
 def timing_enable(on=True, device=None):
     """Turn per-stage GPU timing (HIP events on the call's stream) on or off."""
     ctx = context(device)

@@ -21,8 +21,6 @@ constexpr int EPB = 256;  // tile elements per work-group (one per thread)
 template <int MODE>
 __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
 {
-    constexpr int BM = tile_of(MODE);
-
     GramDesc d;
     int tile;
     if (args.tiles) {
@@ -39,6 +37,9 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
         ++I;
     }
     const int J = I + (tile - base);
+    const int BM = d.bm;
+    if ((int)blockIdx.y * EPB >= BM * BM)
+        return;  // the grid covers the largest tile of the launch
 
     auto part = gptr((const double *)d.partial + (int64_t)tile * 2 * BM * BM);
     const int64_t cstride = (int64_t)d.nupper * 2 * BM * BM;
@@ -47,7 +48,8 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
 
     {
         const int e = blockIdx.y * EPB + threadIdx.x;
-        const int i = e / BM, j = e - (e / BM) * BM;
+        const int lbm = BM == 64 ? 6 : 7;  // the tile edges are 64 and 128
+        const int i = e >> lbm, j = e & (BM - 1);
         const int64_t gi = (int64_t)I * BM + i, gj = (int64_t)J * BM + j;
         if (gi >= n || gj >= n || gi > gj)
             return;
@@ -89,7 +91,7 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
 template <int MODE>
 __global__ __launch_bounds__(256) void diag_kernel(GramDesc d)
 {
-    constexpr int BM = tile_of(MODE);
+    const int BM = d.bm;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= d.n)
         return;
@@ -119,12 +121,11 @@ hipError_t launch_diag(int mode, const GramDesc &g, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, hipStream_t s)
+hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, int bm_max, hipStream_t s)
 {
     if (ntiles <= 0)
         return hipSuccess;
-    const int bm = tile_of(mode);
-    dim3 grid(ntiles, bm * bm / EPB);
+    dim3 grid(ntiles, bm_max * bm_max / EPB);
     switch (mode) {
     case M_F64: epilogue_kernel<M_F64><<<grid, 256, 0, s>>>(a); break;
     case M_F32: epilogue_kernel<M_F32><<<grid, 256, 0, s>>>(a); break;

@@ -53,9 +53,9 @@ constexpr int RB = 64;  // bytes of one row staged per K-stage, per plane
 // LDS ring depth per mode, in stages of planes x 2 panels x BM rows x 64 B.
 // With units of SPI stages the ring holds NS / SPI units: while one is read,
 // the loads of the next NS / SPI - 2 are in flight and one more is issued.
-template <int MODE>
+template <int MODE, int TBM>
 struct Ring {
-    static constexpr int BM = tile_of(MODE);
+    static constexpr int BM = TBM;
     static constexpr int PL = planes_of(MODE);
     static constexpr int PANEL = BM * RB;          // one panel of one plane
     static constexpr int STAGE = PL * 2 * PANEL;   // A and B panels of every plane
@@ -136,22 +136,22 @@ __device__ inline void wait_lgkm0() { __builtin_amdgcn_s_waitcnt(15 | (3 << 14) 
 // (BM/2) x (BM/2) sub-tile: the row panel's blocks (a) and the column
 // panel's blocks (b).  The 16-bit modes take two stages per unit so that a
 // unit's MFMA work stays long next to the barrier that separates units.
-template <int MODE>
+template <int MODE, int BM>
 struct Frags {
-    static constexpr int NB = tile_of(MODE) / 32;
+    static constexpr int NB = BM / 32;
     static constexpr int PL = planes_of(MODE);
     static constexpr int SPI = (MODE == M_BF16 || MODE == M_F16) ? 2 : 1;
     u32x4 a[SPI][PL][NB], b[SPI][PL][NB];
 };
-template <>
-struct Frags<M_F32> {
-    static constexpr int NB = tile_of(M_F32) / 32;
+template <int BM>
+struct Frags<M_F32, BM> {
+    static constexpr int NB = BM / 32;
     static constexpr int SPI = 1;
     float2 a[2][NB], b[2][NB];  // two K-steps of 4 samples
 };
-template <>
-struct Frags<M_F64> {
-    static constexpr int NB = tile_of(M_F64) / 32;
+template <int BM>
+struct Frags<M_F64, BM> {
+    static constexpr int NB = BM / 32;
     static constexpr int SPI = 1;
     double2 a[NB], b[NB];
 };
@@ -174,13 +174,12 @@ typedef const __attribute__((address_space(1))) void gvoid;
 constexpr int WAVES = 8;   // two groups of four waves per work-group
 constexpr int THREADS = 64 * WAVES;
 
-template <int MODE, bool DIAG>
+template <int MODE, int TBM, bool DIAG>
 __device__ inline void herk_tile(const GramDesc &d, const uint8_t *ua, const uint8_t *ub, int I, int J, int nst,
-                                 typename AccOf<MODE>::type (&re)[tile_of(MODE) / 32][tile_of(MODE) / 32],
-                                 typename AccOf<MODE>::type (&im)[tile_of(MODE) / 32][tile_of(MODE) / 32],
-                                 uint8_t *smem)
+                                 typename AccOf<MODE>::type (&re)[TBM / 32][TBM / 32],
+                                 typename AccOf<MODE>::type (&im)[TBM / 32][TBM / 32], uint8_t *smem)
 {
-    typedef Ring<MODE> R;
+    typedef Ring<MODE, TBM> R;
     constexpr int BM = R::BM, NB = BM / 32, PL = R::PL, PANEL = R::PANEL, STAGE = R::STAGE, NS = R::NS;
     constexpr int CB = cbytes_of(MODE);
     constexpr int BLKS = PANEL / 1024;            // 1 KB load blocks per panel and plane
@@ -235,7 +234,7 @@ __device__ inline void herk_tile(const GramDesc &d, const uint8_t *ua, const uin
     // One unit = SPI consecutive stages.  A wave reads all operand fragments
     // of a unit from LDS into registers (Frags), then runs that unit's MFMAs
     // from registers in the next interval.
-    typedef Frags<MODE> F;
+    typedef Frags<MODE, BM> F;
     constexpr int SPI = F::SPI;
     constexpr int NU = NS / SPI;                  // units held by the ring
     constexpr int LPU = SPI * LPS;                // loads per unit per wave
@@ -383,12 +382,11 @@ __device__ inline void herk_tile(const GramDesc &d, const uint8_t *ua, const uin
 }
 
 // Folds group 1's accumulators into group 0's through LDS (after the K loop).
-template <int MODE>
-__device__ inline void fold_groups(typename AccOf<MODE>::type (&re)[tile_of(MODE) / 32][tile_of(MODE) / 32],
-                                   typename AccOf<MODE>::type (&im)[tile_of(MODE) / 32][tile_of(MODE) / 32],
-                                   uint8_t *smem)
+template <int MODE, int BM>
+__device__ inline void fold_groups(typename AccOf<MODE>::type (&re)[BM / 32][BM / 32],
+                                   typename AccOf<MODE>::type (&im)[BM / 32][BM / 32], uint8_t *smem)
 {
-    constexpr int NB = tile_of(MODE) / 32;
+    constexpr int NB = BM / 32;
     typedef typename AccOf<MODE>::type acc_t;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int grp = wave >> 2, wq = wave & 3;
@@ -415,16 +413,22 @@ __device__ inline void fold_groups(typename AccOf<MODE>::type (&re)[tile_of(MODE
     }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
+// Work-groups per CU the launch bounds ask for: the 64-wide tile of the
+// 16-bit and FP32 modes takes half the LDS ring and a quarter of the
+// accumulators, so two work-groups share a CU.
+template <int MODE, int BM>
+constexpr int wg_per_cu() { return (BM == 64 && MODE != M_F64) ? 2 : 1; }
+
+template <int MODE, int BM>
+__global__ __launch_bounds__(THREADS, (wg_per_cu<MODE, BM>())) void herk_kernel(HerkArgs args)
 {
-    constexpr int BM = tile_of(MODE);
     constexpr int NB = BM / 32;  // 16x16 blocks per wave side
     typedef typename AccOf<MODE>::type acc_t;
-    static_assert(Ring<MODE>::NS * Ring<MODE>::STAGE >= 4 * NB * NB * 2 * 64 * (int)sizeof(acc_t),
+    typedef Ring<MODE, BM> R;
+    static_assert(R::NS * R::STAGE >= 4 * NB * NB * 2 * 64 * (int)sizeof(acc_t),
                   "the ring must hold one group's accumulators for the fold");
 
-    __shared__ __attribute__((aligned(1024))) uint8_t smem[Ring<MODE>::NS * Ring<MODE>::STAGE];
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[R::NS * R::STAGE];
 
     // ---- which item
     const int item = xcd_remap(blockIdx.x, gridDim.x);
@@ -472,10 +476,10 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
     const uint8_t *ua = d.u + (int64_t)chunk * d.cstride;
     const uint8_t *ub = (d.ub ? d.ub : d.u) + (int64_t)chunk * d.cstride;
     if (I == J && !d.ub)
-        herk_tile<MODE, true>(d, ua, ub, I, J, nst, re, im, smem);
+        herk_tile<MODE, BM, true>(d, ua, ub, I, J, nst, re, im, smem);
     else
-        herk_tile<MODE, false>(d, ua, ub, I, J, nst, re, im, smem);
-    fold_groups<MODE>(re, im, smem);
+        herk_tile<MODE, BM, false>(d, ua, ub, I, J, nst, re, im, smem);
+    fold_groups<MODE, BM>(re, im, smem);
 
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= 4)
@@ -555,40 +559,68 @@ __global__ __launch_bounds__(THREADS, 1) void herk_kernel(HerkArgs args)
             }
 }
 
-template <int MODE>
+template <int MODE, int BM>
 int occupancy_of()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, herk_kernel<MODE>, THREADS, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, herk_kernel<MODE, BM>, THREADS, 0) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
 }  // namespace
 
-hipError_t launch_herk(int mode, const HerkArgs &a, int nwg, hipStream_t s)
+bool tile_supported(int mode, int bm)
+{
+    return mode == M_F64 ? bm == 64 : (bm == 64 || bm == 128);
+}
+
+hipError_t launch_herk(int mode, int bm, const HerkArgs &a, int nwg, hipStream_t s)
 {
     if (nwg <= 0)
         return hipSuccess;
-    switch (mode) {
-    case M_F64: herk_kernel<M_F64><<<nwg, THREADS, 0, s>>>(a); break;
-    case M_F32: herk_kernel<M_F32><<<nwg, THREADS, 0, s>>>(a); break;
-    case M_SPLIT: herk_kernel<M_SPLIT><<<nwg, THREADS, 0, s>>>(a); break;
-    case M_BF16: herk_kernel<M_BF16><<<nwg, THREADS, 0, s>>>(a); break;
-    case M_F16: herk_kernel<M_F16><<<nwg, THREADS, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
+    if (!tile_supported(mode, bm))
+        return hipErrorInvalidValue;
+    if (bm == 64) {
+        switch (mode) {
+        case M_F64: herk_kernel<M_F64, 64><<<nwg, THREADS, 0, s>>>(a); break;
+        case M_F32: herk_kernel<M_F32, 64><<<nwg, THREADS, 0, s>>>(a); break;
+        case M_SPLIT: herk_kernel<M_SPLIT, 64><<<nwg, THREADS, 0, s>>>(a); break;
+        case M_BF16: herk_kernel<M_BF16, 64><<<nwg, THREADS, 0, s>>>(a); break;
+        case M_F16: herk_kernel<M_F16, 64><<<nwg, THREADS, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (mode) {
+        case M_F32: herk_kernel<M_F32, 128><<<nwg, THREADS, 0, s>>>(a); break;
+        case M_SPLIT: herk_kernel<M_SPLIT, 128><<<nwg, THREADS, 0, s>>>(a); break;
+        case M_BF16: herk_kernel<M_BF16, 128><<<nwg, THREADS, 0, s>>>(a); break;
+        case M_F16: herk_kernel<M_F16, 128><<<nwg, THREADS, 0, s>>>(a); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }
 
-int herk_occupancy(int mode)
+int herk_occupancy(int mode, int bm)
 {
+    if (!tile_supported(mode, bm))
+        return 1;
+    if (bm == 64) {
+        switch (mode) {
+        case M_F64: return occupancy_of<M_F64, 64>();
+        case M_F32: return occupancy_of<M_F32, 64>();
+        case M_SPLIT: return occupancy_of<M_SPLIT, 64>();
+        case M_BF16: return occupancy_of<M_BF16, 64>();
+        case M_F16: return occupancy_of<M_F16, 64>();
+        default: return 1;
+        }
+    }
     switch (mode) {
-    case M_F64: return occupancy_of<M_F64>();
-    case M_F32: return occupancy_of<M_F32>();
-    case M_SPLIT: return occupancy_of<M_SPLIT>();
-    case M_BF16: return occupancy_of<M_BF16>();
-    case M_F16: return occupancy_of<M_F16>();
+    case M_F32: return occupancy_of<M_F32, 128>();
+    case M_SPLIT: return occupancy_of<M_SPLIT, 128>();
+    case M_BF16: return occupancy_of<M_BF16, 128>();
+    case M_F16: return occupancy_of<M_F16, 128>();
     default: return 1;
     }
 }

@@ -44,7 +44,7 @@ struct TimingRec {
 struct plv_ctx {
     int device = -1;
     int cus = 256;
-    int occ[5] = {1, 1, 1, 1, 1};
+    int occ[NOCC] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1};  // Gram work-groups per CU (occ_index)
     std::string err;
     void *staging = nullptr;  // pinned host buffer for the work tables
     size_t staging_bytes = 0;
@@ -53,7 +53,7 @@ struct plv_ctx {
     bool timing = false;
     std::vector<TimingRec> recs;   // recorded, not yet read
     std::vector<hipEvent_t> pool;  // idle events
-    plv::TuneMap tune;             // measured K-chunk counts (plv_autotune)
+    plv::Tuning tune;              // measured K-chunk counts and tile edges (plv_autotune)
     void *scratch = nullptr;       // this device's copy of `scratch` (plv_from_analytic_noalloc)
     hipError_t scratch_err = hipSuccess;
 };
@@ -152,6 +152,26 @@ struct StageTimer {
 };
 
 }  // namespace
+
+// Times `runs` executions of run() between HIP events on stream s, after one
+// untimed execution.  ms < 0 when a launch or event failed (st / e say which).
+template <class F>
+static float time_runs(F run, hipStream_t s, hipEvent_t e0, hipEvent_t e1, int runs, plv_status &st, hipError_t &e)
+{
+    if ((st = run()) != PLV_OK)
+        return -1.0f;
+    if ((e = hipEventRecord(e0, s)) != hipSuccess)
+        return -1.0f;
+    for (int r = 0; r < runs && st == PLV_OK; ++r)
+        st = run();
+    if (st != PLV_OK)
+        return -1.0f;
+    float ms = 0.0f;
+    if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+        (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+        return -1.0f;
+    return ms;
+}
 
 extern "C" {
 
@@ -255,7 +275,9 @@ plv_status plv_create(plv_ctx **out, int device)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
             ctx->cus = cus;
         for (int m = 0; m < 5; ++m)
-            ctx->occ[m] = herk_occupancy(m);
+            for (int bm : {64, 128})
+                if (tile_supported(m, bm))
+                    ctx->occ[occ_index(m, bm)] = herk_occupancy(m, bm);
         if (device < MAX_DEVICES) {
             // once per device, with the device current: its copy of the scratch array
             std::lock_guard<std::mutex> lk(scratch_mu);
@@ -672,7 +694,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
                 ha.pass = p;
                 ha.blocked = plan.blocked ? 1 : 0;
                 const int nch = std::min(d.nslot, d.nchunk - p * d.nslot);
-                if ((e = launch_herk(mode, ha, d.nupper * nch, s)) != hipSuccess)
+                if ((e = launch_herk(mode, d.bm, ha, d.nupper * nch, s)) != hipSuccess)
                     return hip_fail(ctx, e, "gram kernel launch");
                 tm.launched();
             }
@@ -688,26 +710,29 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             tm.launched();
             ea.coherence = true;
         }
-        if ((e = launch_epilogue(mode, ea, d.nupper, s)) != hipSuccess)
+        if ((e = launch_epilogue(mode, ea, d.nupper, d.bm, s)) != hipSuccess)
             return hip_fail(ctx, e, "epilogue kernel launch");
         tm.launched();
         return PLV_OK;
     }
-    HerkArgs ha{};
-    ha.gd = (const GramDesc *)(ws + plan.desc_off);
-    ha.items = (const Item *)(ws + plan.item_off);
-    ha.nitems = (int32_t)items.size();
     {
+        // one launch per tile edge present (each an XCD-major item list)
         StageTimer tm(ctx, PLV_STAGE_GRAM, s);
-        if ((e = launch_herk(mode, ha, (int)items.size(), s)) != hipSuccess)
-            return hip_fail(ctx, e, "gram kernel launch");
-        tm.launched();
+        for (const Plan::ItemGroup &grp : plan.groups) {
+            HerkArgs ha{};
+            ha.gd = (const GramDesc *)(ws + plan.desc_off);
+            ha.items = (const Item *)(ws + plan.item_off) + grp.off;
+            ha.nitems = (int32_t)grp.count;
+            if ((e = launch_herk(mode, grp.bm, ha, (int)grp.count, s)) != hipSuccess)
+                return hip_fail(ctx, e, "gram kernel launch");
+            tm.launched();
+        }
     }
     if (tiles.empty())
         return PLV_OK;
     StageTimer tm(ctx, PLV_STAGE_EPILOGUE, s);
     EpiArgs ea{};
-    ea.gd = ha.gd;
+    ea.gd = (const GramDesc *)(ws + plan.desc_off);
     if (plan.op == PLV_OP_COHERENCE) {
         for (const GramDesc &d : gd)
             if ((e = launch_diag(mode, d, s)) != hipSuccess)
@@ -716,7 +741,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
         ea.coherence = true;
     }
     ea.tiles = (const TileRef *)(ws + plan.tile_off);
-    if ((e = launch_epilogue(mode, ea, (int)tiles.size(), s)) != hipSuccess)
+    if ((e = launch_epilogue(mode, ea, (int)tiles.size(), plan.bm_max, s)) != hipSuccess)
         return hip_fail(ctx, e, "epilogue kernel launch");
     tm.launched();
     return PLV_OK;
@@ -961,7 +986,7 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
         pa.n = g.n;
         pa.tw = g.t;
         pa.kpad = g.kpad;
-        pa.rows = g.ntile_b * tile_of(mode);
+        pa.rows = g.ntile_b * g.bm;
         pa.w = ws + g.w_off;
         pa.plane_bytes = (int64_t)g.plane_bytes;
         if ((e = launch_planes_t(mode, pa, s)) != hipSuccess)
@@ -986,15 +1011,17 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
     if (!plan.grouped) {
         HerkArgs hk{};
         hk.g = gd[0];
-        if ((e = launch_herk(mode, hk, gd[0].nupper, s)) != hipSuccess)
+        if ((e = launch_herk(mode, gd[0].bm, hk, gd[0].nupper, s)) != hipSuccess)
             return hip_fail(ctx, e, "product kernel launch");
     } else {
-        HerkArgs hk{};
-        hk.gd = (const GramDesc *)(ws + plan.desc_off);
-        hk.items = (const Item *)(ws + plan.item_off);
-        hk.nitems = (int32_t)items.size();
-        if ((e = launch_herk(mode, hk, (int)items.size(), s)) != hipSuccess)
-            return hip_fail(ctx, e, "product kernel launch");
+        for (const Plan::ItemGroup &grp : plan.groups) {
+            HerkArgs hk{};
+            hk.gd = (const GramDesc *)(ws + plan.desc_off);
+            hk.items = (const Item *)(ws + plan.item_off) + grp.off;
+            hk.nitems = (int32_t)grp.count;
+            if ((e = launch_herk(mode, grp.bm, hk, (int)grp.count, s)) != hipSuccess)
+                return hip_fail(ctx, e, "product kernel launch");
+        }
     }
     tm.launched();
     // through the normalisation
@@ -1078,11 +1105,14 @@ plv_status plv_backward(plv_ctx *ctx, plv_prec prec, plv_input kind, const plv_p
                             (uint8_t *)ws, (hipStream_t)stream);
 }
 
-// Measures the K-chunk count of a single-problem forward call: the planner's
-// choice and up to two exact splits on either side, each run once untimed and
-// three times between HIP events on the caller's stream; a count replaces the
-// best so far only when it is more than 1% faster.  The winner is kept in the
-// context for every later plan of the same (precision, rows, padded length).
+// Measures the launch shape of a forward call and keeps the fastest in the
+// context.  One problem (one band): the K-chunk count -- the planner's choice
+// and up to two exact splits on either side.  Several problems or bands (a
+// grouped launch): the tile edge of every distinct row count -- the call is
+// run on the problems of that row count alone with each edge.  Each candidate
+// runs once untimed and three times between HIP events on the caller's
+// stream; a candidate replaces the best so far only when it is more than 1%
+// faster.  The winners apply to every later plan on the context.
 plv_status plv_autotune(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
                         const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes, void *stream,
                         int32_t *nchunk)
@@ -1094,40 +1124,26 @@ plv_status plv_autotune(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_proble
     if (op != PLV_OP_FROM_ANALYTIC && op != PLV_OP_FROM_REAL && op != PLV_OP_COHERENCE)
         return fail(ctx, PLV_ERR_INVALID_ARG, "autotune takes a forward op");
     const bool real = op == PLV_OP_FROM_REAL;
+    const plv_band *bb = real ? bands : nullptr;
+    const int32_t nb = real ? nbands : 1;
     Plan plan;
-    plv_status st = begin(ctx, op, prec, probs, nprob, real ? bands : nullptr, real ? nbands : 1, ws, ws_bytes, plan);
+    plv_status st = begin(ctx, op, prec, probs, nprob, bb, nb, ws, ws_bytes, plan);
     if (st != PLV_OK)
         return st;
-    std::vector<int> counts;
-    chunk_counts(plan, counts);
-    if (counts.empty())
-        return PLV_OK;  // grouped launch: one pass, every chunk its own slot
-    const auto key = tune_key(plan);
-    const int cur = plan.grams[0].nchunk;
-    const size_t at = (size_t)(std::lower_bound(counts.begin(), counts.end(), cur) - counts.begin());
-    std::vector<int> cand{cur};
-    for (size_t d = 1; d <= 2; ++d) {
-        if (at >= d)
-            cand.push_back(counts[at - d]);
-        if (at + d < counts.size())
-            cand.push_back(counts[at + d]);
-    }
     const hipStream_t s = (hipStream_t)stream;
-    auto run = [&]() -> plv_status {
+    auto run_on = [&](const plv_problem *pp, int64_t np) -> plv_status {
         if (op == PLV_OP_FROM_ANALYTIC)
-            return plv_from_analytic(ctx, prec, probs, nprob, ws, ws_bytes, stream);
+            return plv_from_analytic(ctx, prec, pp, np, ws, ws_bytes, stream);
         if (op == PLV_OP_COHERENCE)
-            return plv_coherence(ctx, prec, probs, nprob, ws, ws_bytes, stream);
-        return plv_from_real(ctx, prec, probs, nprob, bands, nbands, fs, ws, ws_bytes, stream);
+            return plv_coherence(ctx, prec, pp, np, ws, ws_bytes, stream);
+        return plv_from_real(ctx, prec, pp, np, bands, nbands, fs, ws, ws_bytes, stream);
     };
-    const auto old = ctx->tune.find(key);
-    const bool had = old != ctx->tune.end();
-    const int old_nc = had ? old->second : 0;
-    auto restore = [&]() {
-        if (had)
-            ctx->tune[key] = old_nc;
-        else
-            ctx->tune.erase(key);
+    // the call on these problems fits the caller's workspace
+    auto fits = [&](const plv_problem *pp, int64_t np) {
+        Plan trial;
+        std::string why;
+        return make_plan(ctx->cus, ctx->occ, op, prec, pp, np, bb, nb, trial, why, &ctx->tune) == PLV_OK &&
+               trial.total <= ws_bytes;
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
@@ -1140,46 +1156,119 @@ plv_status plv_autotune(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_proble
     }
     const bool timing = ctx->timing;
     ctx->timing = false;  // the trial runs stay out of the stage timings
-    int best = 0;
-    float best_ms = 0.0f;
-    for (int nc : cand) {
-        ctx->tune[key] = nc;
-        Plan trial;
-        std::string why;
-        if (make_plan(ctx->cus, ctx->occ, op, prec, probs, nprob, real ? bands : nullptr, real ? nbands : 1, trial, why,
-                      &ctx->tune) != PLV_OK ||
-            trial.total > ws_bytes || trial.grams[0].nchunk != nc)
-            continue;  // needs more workspace than the caller gave
-        if ((st = run()) != PLV_OK)
-            break;
-        if ((e = hipEventRecord(e0, s)) != hipSuccess)
-            break;
-        for (int r = 0; r < 3 && st == PLV_OK; ++r)
-            st = run();
-        if (st != PLV_OK)
-            break;
-        float ms = 0.0f;
-        if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
-            (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
-            break;
-        if (best == 0 || ms < best_ms * 0.99f) {
-            best = nc;
-            best_ms = ms;
+    std::vector<int> counts;
+    chunk_counts(plan, counts);
+    if (!counts.empty()) {
+        // ---- one problem: the K-chunk count
+        const auto key = tune_key(plan);
+        const int cur = plan.grams[0].nchunk;
+        const size_t at = (size_t)(std::lower_bound(counts.begin(), counts.end(), cur) - counts.begin());
+        std::vector<int> cand{cur};
+        for (size_t d = 1; d <= 2; ++d) {
+            if (at >= d)
+                cand.push_back(counts[at - d]);
+            if (at + d < counts.size())
+                cand.push_back(counts[at + d]);
+        }
+        const auto old = ctx->tune.chunks.find(key);
+        const bool had = old != ctx->tune.chunks.end();
+        const int old_nc = had ? old->second : 0;
+        int best = 0;
+        float best_ms = 0.0f;
+        for (int nc : cand) {
+            ctx->tune.chunks[key] = nc;
+            Plan trial;
+            std::string why;
+            if (make_plan(ctx->cus, ctx->occ, op, prec, probs, nprob, bb, nb, trial, why, &ctx->tune) != PLV_OK ||
+                trial.total > ws_bytes || trial.grams[0].nchunk != nc)
+                continue;  // needs more workspace than the caller gave
+            const float ms = time_runs([&]() { return run_on(probs, nprob); }, s, e0, e1, 3, st, e);
+            if (ms < 0.0f)
+                break;
+            if (best == 0 || ms < best_ms * 0.99f) {
+                best = nc;
+                best_ms = ms;
+            }
+        }
+        if (st == PLV_OK && e == hipSuccess && best > 0)
+            ctx->tune.chunks[key] = best;
+        else if (had)
+            ctx->tune.chunks[key] = old_nc;
+        else
+            ctx->tune.chunks.erase(key);
+        if (nchunk && st == PLV_OK && e == hipSuccess)
+            *nchunk = best;
+    } else if (plan.mode != M_F64) {
+        // ---- grouped launch: the tile edge of each distinct row count
+        std::vector<int64_t> ns;
+        for (int64_t q = 0; q < nprob; ++q)
+            ns.push_back(probs[q].n);
+        std::sort(ns.begin(), ns.end());
+        ns.erase(std::unique(ns.begin(), ns.end()), ns.end());
+        for (int64_t n : ns) {
+            std::vector<plv_problem> sub;
+            for (int64_t q = 0; q < nprob; ++q)
+                if (probs[q].n == n)
+                    sub.push_back(probs[q]);
+            const auto key = std::make_pair(plan.mode, n);
+            const auto old = ctx->tune.tiles.find(key);
+            const bool had = old != ctx->tune.tiles.end();
+            const int old_bm = had ? old->second : 0;
+            int best = 0;
+            float best_ms = 0.0f;
+            for (int bm : {128, 64}) {
+                ctx->tune.tiles[key] = bm;
+                if (!fits(sub.data(), (int64_t)sub.size()))
+                    continue;
+                const float ms =
+                    time_runs([&]() { return run_on(sub.data(), (int64_t)sub.size()); }, s, e0, e1, 3, st, e);
+                if (ms < 0.0f)
+                    break;
+                if (best == 0 || ms < best_ms * 0.99f) {
+                    best = bm;
+                    best_ms = ms;
+                }
+            }
+            if (st == PLV_OK && e == hipSuccess && best > 0) {
+                ctx->tune.tiles[key] = best;
+            } else {
+                if (had)
+                    ctx->tune.tiles[key] = old_bm;
+                else
+                    ctx->tune.tiles.erase(key);
+                break;
+            }
         }
     }
     ctx->timing = timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (st != PLV_OK || e != hipSuccess) {
-        restore();
-        return st != PLV_OK ? st : hip_fail(ctx, e, "autotune timing");
+    if (st != PLV_OK)
+        return st;
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "autotune timing");
+    return PLV_OK;
+}
+
+plv_status plv_tile_edge(const plv_ctx *ctx, plv_prec prec, int64_t n, int32_t *bm)
+{
+    if (!bm || (int)prec < 0 || (int)prec > 4 || n < 1)
+        return PLV_ERR_INVALID_ARG;
+    *bm = tile_for((int)prec, n, ctx ? &ctx->tune : nullptr);
+    return PLV_OK;
+}
+
+plv_status plv_set_tile_edge(plv_ctx *ctx, plv_prec prec, int64_t n, int32_t bm)
+{
+    if (!ctx || (int)prec < 0 || (int)prec > 4 || n < 1)
+        return PLV_ERR_INVALID_ARG;
+    if (bm == 0) {
+        ctx->tune.tiles.erase(std::make_pair((int)prec, n));
+        return PLV_OK;
     }
-    if (best > 0)
-        ctx->tune[key] = best;
-    else
-        restore();
-    if (nchunk)
-        *nchunk = best;
+    if (!tile_supported((int)prec, bm))
+        return fail(ctx, PLV_ERR_INVALID_ARG, "tile edge %d is not available in this precision", (int)bm);
+    ctx->tune.tiles[std::make_pair((int)prec, n)] = bm;
     return PLV_OK;
 }
 

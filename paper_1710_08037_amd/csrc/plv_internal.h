@@ -68,7 +68,9 @@ __device__ inline uint8_t *plane_at(uint8_t *u, int64_t cstride, int chunk, int6
     return u + c * cstride + plane_off(rows, cb, row, s - c * chunk);
 }
 
-// Tile edge of the Gram kernel for each mode (output tiles are BM x BM).
+// Largest tile edge of the Gram kernel for each mode (output tiles are
+// BM x BM).  The 16-bit and FP32 modes also have a 64-wide tile for small
+// row counts; GramDesc::bm says which edge a problem uses.
 __host__ __device__ constexpr int tile_of(int mode) { return mode == M_F64 ? 64 : 128; }
 // Bytes per complex phasor element in one plane.
 __host__ __device__ constexpr int cbytes_of(int mode) { return mode == M_F64 ? 16 : (mode == M_F32 ? 8 : 4); }
@@ -81,12 +83,13 @@ struct GramDesc {
     int64_t cstride;      // bytes from one chunk block to the next (0: one block)
     int32_t n, npad;      // signals, rows rounded up to the tile (the planes' row count)
     int32_t t, tpad;      // true window length (the 1/T), padded length
-    int32_t ntile;        // tiles per side = npad / BM
+    int32_t ntile;        // tiles per side = npad / bm
     int32_t nupper;       // tiles with I <= J = ntile (ntile + 1) / 2
     int32_t nchunk;       // K-chunks over tpad
     int32_t chunk;        // samples per chunk (multiple of PLV_KGRAN); last may be shorter
     int32_t nslot;        // partial slots (chunks per pass); passes = ceil(nchunk / nslot)
     int32_t fused;        // 1: one chunk, the Gram kernel stores the measures itself
+    int32_t bm;           // tile edge BM of this problem (64 or 128; 64 in F64 mode)
     double *partial;      // [nslot][nupper][2][BM][BM] FP64 chunk sums (unused when fused)
     void *plv, *iplv, *ciplv, *g;  // outputs, [n][n] (g complex interleaved)
     // General product mode (used by the backward): C = A B^H over the full
@@ -280,14 +283,18 @@ struct BwdNormArgs {        // zbar = i Im(conj(u) ubar) u / |z|
 constexpr int MAX_GRID_Y = 65535;
 // Each returns hipSuccess or the launch error.
 hipError_t launch_normalise(int mode, const NormArgs &a, hipStream_t s);
-hipError_t launch_herk(int mode, const HerkArgs &a, int nwg, hipStream_t s);
-hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, hipStream_t s);
+// Every problem a launch reaches must have GramDesc::bm == bm.
+hipError_t launch_herk(int mode, int bm, const HerkArgs &a, int nwg, hipStream_t s);
+// Tile edges the Gram kernel has for a mode.
+bool tile_supported(int mode, int bm);
+// bm_max: the largest tile edge among the tiles (the grid covers it)
+hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, int bm_max, hipStream_t s);
 hipError_t launch_row_scale(bool f64, const ScaleArgs &a, hipStream_t s);
 hipError_t launch_trial_planes(int mode, const TrialArgs &a, hipStream_t s);
 // d[i] = fixed-order sum over slots of the diagonal entries of G's partials
 hipError_t launch_diag(int mode, const GramDesc &g, hipStream_t s);
-// Occupancy (work-groups per CU) of the Gram kernel of `mode`.
-int herk_occupancy(int mode);
+// Occupancy (work-groups per CU) of the Gram kernel of `mode` with tile edge bm.
+int herk_occupancy(int mode, int bm);
 // FFT stage (fft.hip).  f64 selects double precision tables and transforms.
 constexpr int FFT_MAXLOG_F32 = 13;  // M <= 8192 complex FP32 transforms in LDS
 constexpr int FFT_MAXLOG_F64 = 12;  // M <= 4096 complex FP64

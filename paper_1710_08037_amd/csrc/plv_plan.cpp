@@ -98,17 +98,24 @@ void choose_chunks_grouped(GramPlan &g, int maxc)
 // A plain longest-first order of items would hand XCD 0 all the longest ones.
 constexpr int NXCD = 8;
 
-void schedule_items(Plan &plan)
+// One XCD-major item list for the problems with tile edge bm, appended to
+// plan.items as one launch group.
+void schedule_group(Plan &plan, int bm)
 {
     const size_t np = plan.grams.size();
-    std::vector<std::pair<double, size_t>> cost(np);
+    std::vector<std::pair<double, size_t>> cost;
     for (size_t q = 0; q < np; ++q) {
         const GramPlan &g = plan.grams[q];
+        if (g.bm != bm)
+            continue;
         double c = 0.0;
         for (int k = 0; k < g.nchunk; ++k)  // product mode (backward): K = kpad
             c += (g.kpad > 0 ? g.kpad : std::min(g.chunk, g.tpad - k * g.chunk)) + ITEM_OVERHEAD;
-        cost[q] = {c * g.nupper, q};
+        // a 64-wide tile does a quarter of a 128-wide tile's MFMA work
+        cost.push_back({c * g.nupper * (double)bm * bm / (128.0 * 128.0), q});
     }
+    if (cost.empty())
+        return;
     std::stable_sort(cost.begin(), cost.end(),
                      [](const std::pair<double, size_t> &a, const std::pair<double, size_t> &b) {
                          return a.first > b.first;
@@ -129,9 +136,10 @@ void schedule_items(Plan &plan)
     size_t len = 0;
     for (int x = 0; x < NXCD; ++x)
         len = std::max(len, count[x]);
-    plan.items.assign(len * NXCD, Item{-1, 0, 0, 0});
+    const size_t base = plan.items.size();
+    plan.items.resize(base + len * NXCD, Item{-1, 0, 0, 0});
     for (int x = 0; x < NXCD; ++x) {
-        size_t k = (size_t)x * len;
+        size_t k = base + (size_t)x * len;
         for (size_t q : lists[x]) {
             const GramPlan &g = plan.grams[q];
             for (int c = 0; c < g.nchunk; ++c)
@@ -139,13 +147,43 @@ void schedule_items(Plan &plan)
                     plan.items[k++] = Item{(int32_t)q, t, c, 0};
         }
     }
+    plan.groups.push_back(Plan::ItemGroup{bm, base, len * NXCD});
+}
+
+void schedule_items(Plan &plan)
+{
+    plan.items.clear();
+    plan.groups.clear();
+    schedule_group(plan, 128);
+    schedule_group(plan, 64);
     plan.nitems = plan.items.size();
 }
 
 }  // namespace
 
+int model_tile(int mode, int64_t n)
+{
+    if (mode == M_F64)
+        return 64;
+    auto work = [n](int bm) {
+        const double nt = (double)((n + bm - 1) / bm);
+        return nt * (nt + 1.0) / 2.0 * bm * bm;
+    };
+    return work(64) / 0.85 < work(128) ? 64 : 128;
+}
+
+int tile_for(int mode, int64_t n, const Tuning *tune)
+{
+    if (tune) {
+        const auto it = tune->tiles.find(std::make_pair(mode, n));
+        if (it != tune->tiles.end() && tile_supported(mode, it->second))
+            return it->second;
+    }
+    return model_tile(mode, n);
+}
+
 plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
-                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why, const TuneMap *tune)
+                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why, const Tuning *tune)
 {
     plan = Plan();
     if ((int)prec < 0 || (int)prec > 4) {
@@ -190,7 +228,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
     const int mode = (int)prec;
     plan.mode = mode;
     plan.op = op;
-    const int bm = tile_of(mode);
+    const bool backward = (op == PLV_OP_BACKWARD_ANALYTIC || op == PLV_OP_BACKWARD_REAL);
     const int cb = cbytes_of(mode);
     const int pl = planes_of(mode);
     const size_t in_elem = (mode == M_F64 ? 8 : 4) * (real ? 1 : 2);
@@ -234,10 +272,14 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
             why = msg("problem %lld: backward needs the forward's complex G in `g`", q);
             return PLV_ERR_INVALID_ARG;
         }
+        // the backward's product runs on the largest tile; a forward problem
+        // takes the measured or modelled edge for its row count
+        const int bm = backward ? tile_of(mode) : tile_for(mode, p.n, tune);
         for (int b = 0; b < nbands; ++b) {
             GramPlan g;
             g.prob = q;
             g.band = b;
+            g.bm = bm;
             g.n = (int)p.n;
             g.npad = (int)((p.n + bm - 1) / bm * bm);
             g.t0 = (int)p.t0;
@@ -255,13 +297,13 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         }
     }
 
-    const bool backward = (op == PLV_OP_BACKWARD_ANALYTIC || op == PLV_OP_BACKWARD_REAL);
     if (backward && (mode == M_BF16 || mode == M_F16)) {
         // the backward operand H is unbounded: plain 16-bit phasors are not
         // accurate enough for it, so these modes run their adjoint in split form
         plan.mode = M_SPLIT;
     }
-    const int slots = std::max(1, cus) * std::max(1, occ ? occ[mode] : 1);
+    for (const GramPlan &g : plan.grams)
+        plan.bm_max = std::max(plan.bm_max, g.bm);
     const bool grouped = plan.grams.size() > 1;
     plan.grouped = grouped;
     // device tables: Gram problem descriptors always (the FFT stage reads them
@@ -274,7 +316,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         // general product tiles: rows of H x rows of W, one K-chunk (K = n)
         for (GramPlan &g : plan.grams) {
             g.kpad = (g.n + PLV_KGRAN - 1) / PLV_KGRAN * PLV_KGRAN;
-            g.ntile_b = (g.t + bm - 1) / bm;
+            g.ntile_b = (g.t + g.bm - 1) / g.bm;
             g.nupper = g.ntile * g.ntile_b;
             g.chunk = g.kpad;
             g.nchunk = 1;
@@ -309,10 +351,12 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
     } else {
         int forced = 0;
         if (tune) {
-            const auto it = tune->find(tune_key(plan));
-            if (it != tune->end())
+            const auto it = tune->chunks.find(tune_key(plan));
+            if (it != tune->chunks.end())
                 forced = it->second;
         }
+        const int bm = plan.grams[0].bm;
+        const int slots = std::max(1, cus) * std::max(1, occ ? occ[occ_index(mode, bm)] : 1);
         choose_chunks_single(plan.grams[0], slots, bm, MAX_CHUNK, forced);
         plan.grams[0].fused = plan.grams[0].nchunk == 1 && op != PLV_OP_COHERENCE;
         plan.blocked = true;
@@ -423,7 +467,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         const int bpl = planes_of(plan.mode), bcb = cbytes_of(plan.mode);
         const size_t csz = mode == M_F64 ? 16 : 8;
         for (GramPlan &g : plan.grams) {
-            const size_t rows = (size_t)std::max(g.npad, g.ntile_b * bm);
+            const size_t rows = (size_t)std::max(g.npad, g.ntile_b * g.bm);
             g.plane_bytes = align256(rows * g.kpad * bcb);
             g.u_off = off;
             off += g.plane_bytes * bpl;
@@ -449,7 +493,7 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         if (g.fused)
             continue;
         g.part_off = off;
-        off += align256((size_t)g.nslot * g.nupper * 2 * bm * bm * sizeof(double));
+        off += align256((size_t)g.nslot * g.nupper * 2 * g.bm * g.bm * sizeof(double));
     }
     if (op == PLV_OP_COHERENCE) {
         for (GramPlan &g : plan.grams) {
@@ -481,6 +525,7 @@ void fill_descs(const Plan &plan, uint8_t *ws, std::vector<GramDesc> &gd)
         d.chunk = g.chunk;
         d.nslot = g.nslot;
         d.fused = g.fused ? 1 : 0;
+        d.bm = g.bm;
         d.partial = g.fused ? nullptr : (double *)(ws + g.part_off);
         d.diag = plan.op == PLV_OP_COHERENCE ? (double *)(ws + g.diag_off) : nullptr;
         d.plv = g.plv;

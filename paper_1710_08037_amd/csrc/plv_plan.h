@@ -22,6 +22,7 @@ struct GramPlan {
     int band = 0;
     int n = 0, npad = 0;
     int t = 0, t0 = 0, tpad = 0;       // window length, window start, padded length
+    int bm = 0;                        // tile edge (64 or 128)
     int ntile = 0, nupper = 0;
     int nchunk = 0, chunk = 0, nslot = 0;
     bool fused = false;                // one chunk: the Gram kernel stores the measures
@@ -63,6 +64,12 @@ struct Plan {
     bool blocked = false;                     // single Gram problem: blocked tile order (tile_order.h)
     size_t nitems = 0, ntiles = 0;
     std::vector<Item> items;                  // grouped launch: work items, XCD-major (see schedule_items)
+    struct ItemGroup {
+        int bm;                               // tile edge of every problem in the group
+        size_t off, count;                    // its run of `items` (one launch)
+    };
+    std::vector<ItemGroup> groups;            // one per tile edge present, 128 first
+    int bm_max = 0;                           // largest tile edge among the problems
     bool grouped = false;                     // Gram work from the item table
     // real input only
     std::vector<FftPlan> fft;                 // per problem
@@ -78,15 +85,34 @@ struct Plan {
     size_t total = 0;
 };
 
-// Checks the arguments and lays out the workspace.  `occ` (work-groups per CU
-// of the Gram kernel, per mode) may be NULL: then 1 is assumed.
-// K-chunk counts measured by plv_autotune for single-problem launches, keyed
-// by (mode, rows, padded length); make_plan uses them in place of its model.
+// Measured choices that replace the planner's cost models (plv_autotune):
+//   chunks: K-chunk counts of single-problem launches, keyed by (mode, rows,
+//           padded length);
+//   tiles:  the tile edge of a forward problem, keyed by (mode, rows).
 typedef std::map<std::tuple<int, int64_t, int64_t>, int> TuneMap;
+typedef std::map<std::pair<int, int64_t>, int> TileMap;
+struct Tuning {
+    TuneMap chunks;
+    TileMap tiles;
+};
 
+// Work-groups per CU of the Gram kernel, per mode and tile edge:
+// occ[2 * mode + (bm == 64)].
+constexpr int NOCC = 10;
+inline int occ_index(int mode, int bm) { return 2 * mode + (bm == 64 ? 1 : 0); }
+
+// The planner's tile edge for a forward problem of n rows: the one with the
+// smaller whole-tile MFMA work over the upper triangle, the 64-wide tile's
+// work counted 1/0.85 times (its shorter MFMA runs per barrier).
+int model_tile(int mode, int64_t n);
+// The tile edge a forward problem of n rows gets: measured, else the model's.
+int tile_for(int mode, int64_t n, const Tuning *tune);
+
+// Checks the arguments and lays out the workspace.  `occ` (NOCC entries, see
+// occ_index) may be NULL: then 1 is assumed.
 plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
                      const plv_band *bands, int32_t nbands, Plan &plan, std::string &why,
-                     const TuneMap *tune = nullptr);
+                     const Tuning *tune = nullptr);
 
 // The K-chunk counts a single-problem plan can take (every chunk but the last
 // the same whole number of granules), ascending; empty for a grouped plan.

@@ -126,3 +126,40 @@ def test_null_context_rejected():
     arr = _abi.problems([_prob()])
     assert _abi.lib().plv_from_analytic(None, 2, arr, 1, None, 0, None) == 1
     assert _abi.lib().plv_destroy(None) == 1
+
+
+def test_tile_edge_model_and_overrides(host_ctx):
+    L = _abi.lib()
+    bm = C.c_int32(0)
+
+    def edge(ctx, prec, n):
+        assert L.plv_tile_edge(ctx, prec, n, C.byref(bm)) == 0
+        return bm.value
+
+    # whole-tile MFMA work over the upper triangle, the 64-wide tile's
+    # counted 1/0.85 times: small row counts take the 64-wide tile
+    for n, want in ((1, 64), (68, 64), (148, 64), (360, 128), (1000, 128), (1024, 128), (15000, 128)):
+        assert edge(None, 2, n) == want, n
+    assert edge(None, 0, 1000) == 64  # FP64 has only the 64-wide tile
+    assert L.plv_set_tile_edge(host_ctx, 2, 1000, 64) == 0
+    assert edge(host_ctx, 2, 1000) == 64
+    assert edge(host_ctx, 1, 1000) == 128  # per precision
+    assert L.plv_set_tile_edge(host_ctx, 2, 1000, 0) == 0
+    assert edge(host_ctx, 2, 1000) == 128
+    assert L.plv_set_tile_edge(host_ctx, 2, 1000, 96) == 1
+    assert L.plv_set_tile_edge(host_ctx, 0, 1000, 128) == 1
+    assert L.plv_tile_edge(None, 2, 0, C.byref(bm)) == 1
+
+
+def test_workspace_follows_the_tile_edge(host_ctx):
+    L = _abi.lib()
+    # n = 148, one chunk: phasor planes of npad rows x tpad samples x 8 B (split),
+    # npad = 192 with the 64-wide tile and 256 with the 128-wide one
+    st, a = _ws(host_ctx, [_prob(148, 1000), _prob(148, 1000)])
+    assert st == 0
+    assert L.plv_set_tile_edge(host_ctx, 2, 148, 128) == 0
+    st, b = _ws(host_ctx, [_prob(148, 1000), _prob(148, 1000)])
+    assert L.plv_set_tile_edge(host_ctx, 2, 148, 0) == 0
+    assert st == 0
+    planes = 2 * 64 * 1024 * 8  # 64 more padded rows per problem
+    assert planes - 4096 <= b - a <= planes  # less the smaller item table
