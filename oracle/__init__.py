@@ -28,6 +28,10 @@ What is computed, and where it comes from in the paper (Bruna, Maestu, Pereda,
                     rows' powers (coherence = |C|); ``full_coherence``.
 * ``full_over_trials`` Eq. 1 (matrix form Eq. 8): Lachaux's PLV(t), the mean
                     over trials at each time point.
+* ``stft_bins``     Section II.B, Eq. 12's X_i(f, n): DFT bins of windowed
+                    segments (``window``: symmetric Hamming, Hann or
+                    rectangular), by plain DFT sums; ``full_coherence_stft``
+                    the coherency over segments at each bin.
 
 Readings of the paper that the oracle takes (orientation of G, absolute
 iPLV/ciPLV, the 1/T normaliser, the z = 0 rule, the ciPLV radicand) are listed
@@ -277,6 +281,58 @@ def full_coherence(z: np.ndarray, nthreads=None) -> dict:
     cc[d, d] = coherency(z, np.stack([d, d], 1), nthreads)
     out["c"] = cc
     return out
+
+
+WINDOWS = ("hamming", "hann", "rect")
+
+
+def window(name: str, seg: int) -> np.ndarray:
+    """Segment window of length seg, symmetric (the last sample repeats the
+    first): Hamming 0.54 - 0.46 cos(2 pi m / (seg - 1)), Hann
+    0.5 - 0.5 cos(2 pi m / (seg - 1)), or rectangular (all 1).  The paper's
+    coherence segments are Hamming-windowed (Section III.B, Figure 2)."""
+    m = np.arange(seg, dtype=np.float64)
+    if name == "rect" or seg == 1:
+        return np.ones(seg)
+    c = np.cos(2.0 * np.pi * m / (seg - 1))
+    if name == "hamming":
+        return 0.54 - 0.46 * c
+    if name == "hann":
+        return 0.5 - 0.5 * c
+    raise ValueError("window must be one of %s" % (WINDOWS,))
+
+
+def stft_bins(x: np.ndarray, seg: int, hop: int, k_lo: int, k_hi: int, win: str = "hamming",
+              span=None) -> np.ndarray:
+    """Fourier coefficients of windowed segments, the X_i(f, n) of Section
+    II.B, Eq. 12: segment n of row i covers samples s0 + n*hop + m,
+    m = 0..seg-1, of the span [s0, s1) (the whole row by default), and
+        X_i(k, n) = sum_m w[m] x_i(s0 + n*hop + m) exp(-2 pi i (k m mod seg) / seg)
+    for the DFT bins k = k_lo..k_hi of the segment length; the number of
+    segments is floor((s1 - s0 - seg) / hop) + 1.  A plain DFT (a matrix
+    product with the twiddle matrix), FP64.  Returns [k_hi - k_lo + 1][n][S]."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[None]
+    s0, s1 = (0, x.shape[1]) if span is None else (int(span[0]), int(span[1]))
+    nseg = (s1 - s0 - seg) // hop + 1
+    assert nseg >= 1 and 0 <= k_lo <= k_hi
+    w = window(win, seg)
+    idx = s0 + np.arange(nseg)[:, None] * hop + np.arange(seg)[None, :]   # [S][seg]
+    segs = x[:, idx] * w[None, None, :]                                    # [n][S][seg]
+    k = np.arange(k_lo, k_hi + 1)
+    m = np.arange(seg)
+    tw = np.exp(-2j * np.pi * ((k[:, None] * m[None, :]) % seg) / seg)     # [nbins][seg]
+    return np.einsum("nsm,km->kns", segs, tw)
+
+
+def full_coherence_stft(x: np.ndarray, seg: int, hop: int, k_lo: int, k_hi: int, win: str = "hamming",
+                        span=None, nthreads=None) -> list:
+    """Coherency between every pair of rows at each bin k_lo..k_hi over the
+    windowed segments (Eq. 12 with n running over segments): one
+    full_coherence dict per bin."""
+    z = stft_bins(x, seg, hop, k_lo, k_hi, win, span)
+    return [full_coherence(zk, nthreads) for zk in z]
 
 
 def metrics(g: np.ndarray):
