@@ -373,6 +373,34 @@ def bench_coherence(args):
                     ps / (ms / 1e3), ms, args, DTYPE[prec], {"n": n, "t": t, "prec": prec}, extra)
 
 
+def bench_coherence_stft(args):
+    """Coherency over windowed segments (Section II.B, Eq. 12; Section III.B's
+    Hamming-windowed overlapping segments): N = 1024 real f32 signals x 60 s
+    at 1 kHz (lagged oscillators, 32 latents at 8-12 Hz), 1000-sample Hamming
+    segments with 500 samples of overlap (119 segments), the five 1 Hz bins
+    8..12 Hz; one coherency matrix per bin."""
+    import numpy as np
+    import torch
+
+    import paper_1710_08037_amd as plv
+    import synth
+
+    n, t, seg, hop, bins = N_SIG, T_SAMP, 1000, 500, (8, 12)
+    x = torch.from_numpy(synth.glag_real(n, t, FS, 32, (8.0, 12.0), seed=synth.seed_for(6, 7),
+                                         dtype=np.float32)).cuda()
+    prec = args.prec_batch
+    ms, stages = timed(lambda: plv.coherence_stft(x, seg, hop, bins, "hamming", prec=prec), args.steps,
+                       args.warmup)
+    nseg = (t - seg) // hop + 1
+    nb = bins[1] - bins[0] + 1
+    ps = n * (n - 1) // 2 * nseg * nb
+    extra = {"stage_ms": stages, "segments": nseg, "bins": nb,
+             "coefficients_per_s": round(n * nseg * nb / (stages.get("stft", ms) / 1e3), 1)}
+    return line_for("coherency over segments: N=1024 real f32 x T=60000 at 1 kHz, 1000-sample Hamming segments, "
+                    "500 overlap, bins 8..12 Hz", ps / (ms / 1e3), ms, args, DTYPE[prec],
+                    {"n": n, "t": t, "seg": seg, "hop": hop, "bins": list(bins), "prec": prec}, extra)
+
+
 def bench_trials(args):
     """Lachaux's PLV across trials (Eq. 1): 148 signals x 40 trials x 4000 time
     points (4 s at 1 kHz), complex64 trial-major; one PLV matrix per time point."""
@@ -500,7 +528,8 @@ def main():
                     help="paths to time (both: split-BF16 for `value`, FP32 beside it)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes 3 times (counter calibration) and exit")
-    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain", "coherence", "trials", "fir"])
+    ap.add_argument("--workload", default="sensor", choices=["sensor", "small", "batch", "grad", "brain", "coherence", "trials", "fir",
+                             "coherence_stft"])
     ap.add_argument("--prec-batch", default="split_bf16", help="precision of the batch and grad workloads")
     ap.add_argument("--autotune", action="store_true",
                     help="batch workload: measure the tile edge per row count (plv_autotune) before timing")
@@ -526,7 +555,8 @@ def main():
         return
     if args.workload != "sensor":
         fn = {"small": bench_small, "batch": bench_batch, "grad": bench_grad, "brain": bench_brain, "fir": bench_fir,
-              "coherence": bench_coherence, "trials": bench_trials}[args.workload]
+              "coherence": bench_coherence, "trials": bench_trials,
+              "coherence_stft": bench_coherence_stft}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     z_np = synth.glag_analytic(N_SIG, T_SAMP, FS, 32, (8.0, 12.0), seed=synth.seed_for(2), dtype=np.complex64)

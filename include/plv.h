@@ -166,6 +166,7 @@ typedef enum {
     PLV_STAGE_GRAM = 2,      /* the Gram contraction on MFMA (all its launches)   */
     PLV_STAGE_EPILOGUE = 3,  /* chunk sum, metrics and mirrored store             */
     PLV_STAGE_BACKWARD = 4,  /* adjoint kernels of plv_backward                   */
+    PLV_STAGE_STFT = 5,      /* windowed-segment DFT bins (plv_coherence_stft)   */
     PLV_NSTAGES = 8
 } plv_stage;
 
@@ -262,6 +263,41 @@ plv_status plv_from_analytic_noalloc(plv_ctx *ctx, plv_prec prec, const plv_prob
  * store.  Outputs are [1][n][n]. */
 plv_status plv_coherence(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob, void *ws,
                          size_t ws_bytes, void *stream);
+
+/* Coherency of real signals over windowed segments (Section II.B, Eq. 12,
+ * with the Fourier coefficients X_i(f, n) of segments n; Section III.B
+ * computes coherence on Hamming-windowed segments with overlap).  Segment n
+ * of a row covers samples t0 + n*hop + m, m = 0..seg-1, of its window
+ * [t0, t1); there are S = floor((t1 - t0 - seg) / hop) + 1 >= 1 segments.
+ * For every bin k = k_lo..k_hi of the segment length (frequency k*fs/seg):
+ *   X_i(k, n) = sum_m w[m] x_i(t0 + n*hop + m) exp(-2 pi i k m / seg),
+ *   C_ij(k)   = sum_n X_i(k,n) conj(X_j(k,n)) / sqrt(sum_n |X_i|^2 sum_n |X_j|^2),
+ * and the outputs as plv_coherence gives them (`plv` <- coherence |C|,
+ * `iplv` <- |Im C|, `ciplv` <- |Im C| / sqrt(1 - (Re C)^2), `g` <- C), one
+ * [n][n] matrix per bin: outputs are [k_hi - k_lo + 1][n][n].  Windows are
+ * symmetric: Hamming 0.54 - 0.46 cos(2 pi m / (seg - 1)), Hann
+ * 0.5 - 0.5 cos(2 pi m / (seg - 1)), or rectangular.  `in` holds real rows
+ * (f32; f64 for PLV_PREC_F64), 4-byte (8-byte) aligned; every problem of a
+ * call uses the same segmentation.  Steps: twiddle and window tables ->
+ * segment DFT bins (FP32; FP64 in PLV_PREC_F64) into the workspace -> the
+ * coherency path of plv_coherence over the segments, all bins and problems
+ * in one grouped launch.  Errors as for plv_coherence; PLV_ERR_INVALID_ARG
+ * when the segmentation is out of range or a window holds no whole segment. */
+typedef enum { PLV_WINDOW_HAMMING = 0, PLV_WINDOW_HANN = 1, PLV_WINDOW_RECT = 2 } plv_window;
+#define PLV_STFT_MAX_SEG 4096
+typedef struct {
+    int32_t seg;      /* segment length, 2 <= seg <= PLV_STFT_MAX_SEG              */
+    int32_t hop;      /* samples between segment starts, >= 1 (seg - overlap)      */
+    int32_t k_lo;     /* DFT bins of a segment, 0 <= k_lo <= k_hi <= seg / 2;      */
+    int32_t k_hi;     /*   at most 512 bins                                        */
+    int32_t window;   /* plv_window                                                */
+    int32_t reserved; /* 0                                                         */
+} plv_stft;
+
+plv_status plv_coherence_stft_workspace_size(const plv_ctx *ctx, plv_prec prec, const plv_problem *probs,
+                                             int64_t nprob, const plv_stft *stft, size_t *bytes);
+plv_status plv_coherence_stft(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                              const plv_stft *stft, void *ws, size_t ws_bytes, void *stream);
 
 /* Lachaux's time-resolved PLV across trials (Eq. 1; matrix form Eq. 8): for
  * every time point t of [t0, t1), the measures of the n signals with the

@@ -8,7 +8,7 @@ the library, the first call does, and raises if it has not been built.
 from . import _abi  # noqa: F401
 
 __all__ = ["from_analytic", "from_analytic_noalloc", "from_analytic_batch", "from_real", "from_real_batch", "coherence", "coherence_batch",
-           "over_trials", "backward_batch",
+           "over_trials", "backward_batch", "coherence_stft", "coherence_stft_batch",
            "PLVFunction", "plv_metrics", "timing_enable", "timing_read", "timing_list", "autotune", "autotune_batch", "tile_edge",
            "set_tile_edge"]
 

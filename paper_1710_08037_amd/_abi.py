@@ -33,6 +33,14 @@ class Band(C.Structure):
     _fields_ = [("f_lo", C.c_double), ("f_hi", C.c_double), ("fir_order", C.c_int32), ("reserved", C.c_int32)]
 
 
+class Stft(C.Structure):
+    _fields_ = [("seg", C.c_int32), ("hop", C.c_int32), ("k_lo", C.c_int32), ("k_hi", C.c_int32),
+                ("window", C.c_int32), ("reserved", C.c_int32)]
+
+
+WINDOW = {"hamming": 0, "hann": 1, "rect": 2}
+
+
 class Grad(C.Structure):
     _fields_ = [("dplv", C.c_void_p), ("diplv", C.c_void_p), ("dciplv", C.c_void_p), ("din", C.c_void_p)]
 
@@ -42,9 +50,9 @@ EXPORTS = ("plv_create", "plv_destroy", "plv_status_str", "plv_last_error", "plv
            "plv_timing_enable", "plv_timing_read", "plv_timing_list",
            "plv_workspace_size", "plv_from_analytic", "plv_from_analytic_noalloc", "plv_from_real", "plv_coherence",
            "plv_trials_workspace_size", "plv_over_trials", "plv_backward", "plv_autotune",
-           "plv_tile_edge", "plv_set_tile_edge")
+           "plv_tile_edge", "plv_set_tile_edge", "plv_coherence_stft_workspace_size", "plv_coherence_stft")
 
-STAGES = ("hilbert", "normalise", "gram", "epilogue", "backward")
+STAGES = ("hilbert", "normalise", "gram", "epilogue", "backward", "stft")
 NSTAGES = 8
 
 
@@ -109,6 +117,12 @@ def lib():
             L.plv_autotune.argtypes = [P, C.c_int, C.c_int, C.POINTER(Problem), C.c_int64, C.POINTER(Band), C.c_int32,
                                        C.c_double, P, C.c_size_t, P, C.POINTER(C.c_int32)]
             L.plv_autotune.restype = C.c_int
+            L.plv_coherence_stft_workspace_size.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64,
+                                                            C.POINTER(Stft), C.POINTER(C.c_size_t)]
+            L.plv_coherence_stft_workspace_size.restype = C.c_int
+            L.plv_coherence_stft.argtypes = [P, C.c_int, C.POINTER(Problem), C.c_int64, C.POINTER(Stft), P,
+                                             C.c_size_t, P]
+            L.plv_coherence_stft.restype = C.c_int
             L.plv_tile_edge.argtypes = [P, C.c_int, C.c_int64, C.POINTER(C.c_int32)]
             L.plv_tile_edge.restype = C.c_int
             L.plv_set_tile_edge.argtypes = [P, C.c_int, C.c_int64, C.c_int32]

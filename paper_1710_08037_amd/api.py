@@ -263,6 +263,50 @@ def autotune(x, prec="split_bf16", window=None, fs=None, bands=None, coherence=F
     return chosen.value
 
 
+def coherence_stft_batch(xs, seg, hop, bins, window="hamming", prec="split_bf16", windows=None, want=ALL,
+                         want_g=False):
+    """Coherency of real rows over windowed segments (Section II.B, Eq. 12,
+    the coefficients of segments of `seg` samples, `hop` apart) at the DFT
+    bins bins = (k_lo, k_hi) of the segment length, through
+    plv_coherence_stft: one call, every problem and bin in one grouped launch.
+
+    xs: list of real GPU tensors [n_k, t_k] (float32; float64 for f64);
+    windows: optional [t0, t1) per problem (segments start at t0).
+    Returns a list of dicts of [nbins, n_k, n_k] tensors: 'coh' (coherence),
+    'icoh' (|Im C|), 'cicoh' (corrected imaginary coherency), 'c' (C).
+    `want` names the real outputs by their PLV-field names (plv, iplv, ciplv).
+    """
+    p = _prec_id(prec)
+    dev = xs[0].device
+    rd = torch.float64 if p == 0 else torch.float32
+    cd = torch.complex128 if p == 0 else torch.complex64
+    st = _abi.Stft(int(seg), int(hop), int(bins[0]), int(bins[1]), _abi.WINDOW[window], 0)
+    nb = int(bins[1]) - int(bins[0]) + 1
+    outs, probs = [], []
+    for k, x in enumerate(xs):
+        if x.dtype != rd:
+            raise TypeError("prec %s needs %s input, got %s" % (prec, rd, x.dtype))
+        o = _outputs(x.shape[0], nb, rd, cd, dev, want, want_g)
+        outs.append(o)
+        probs.append(_problem(x, None if windows is None else windows[k], o))
+    arr = _abi.problems(probs)
+    ctx = context(dev)
+    nbytes = C.c_size_t(0)
+    _abi.check(_abi.lib().plv_coherence_stft_workspace_size(ctx.handle, p, arr, len(probs), C.byref(st),
+                                                            C.byref(nbytes)), ctx.handle)
+    ws = torch.empty(max(nbytes.value, 256), dtype=torch.uint8, device=dev)
+    _abi.check(_abi.lib().plv_coherence_stft(ctx.handle, p, arr, len(probs), C.byref(st), C.c_void_p(ws.data_ptr()),
+                                             ws.numel(), _stream(dev)), ctx.handle)
+    names = {"plv": "coh", "iplv": "icoh", "ciplv": "cicoh", "g": "c"}
+    return [{names[k]: v for k, v in o.items()} for o in outs]
+
+
+def coherence_stft(x, seg, hop, bins, window="hamming", prec="split_bf16", span=None, want=ALL, want_g=False):
+    """coherence_stft_batch for one problem."""
+    return coherence_stft_batch([x], seg, hop, bins, window, prec, None if span is None else [span], want,
+                                want_g)[0]
+
+
 def autotune_batch(xs, prec="split_bf16", fs=None, bands=None, windows=None, coherence=False):
     """Measure the tile edge of every distinct row count of a grouped forward
     call (several problems, or real rows with several bands) through

@@ -26,6 +26,7 @@ SOURCES = [
     "epilogue.hip",
     "fft.hip",
     "backward.hip",
+    "stft.hip",
 ]
 
 CFLAGS = [

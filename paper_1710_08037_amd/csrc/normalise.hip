@@ -46,9 +46,10 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
     const real_t sc = a.scale ? (real_t)a.scale[row] : (real_t)1;  // a power of two: exact
     cplx_t zin[VEC];
     if constexpr (MODE != M_F64) {
-        // complex64 rows starting on a 16-byte boundary: the 4 samples as two
-        // 16-byte loads (half the load instructions of per-sample loads)
-        if ((((int64_t)row * a.ld + a.t0) & 1) == 0 && s0 + VEC <= a.tw) {
+        // the 4 samples on a 16-byte boundary (s0 is a multiple of 4, so the
+        // row's first window sample must be): two 16-byte loads, half the
+        // load instructions of per-sample loads
+        if ((reinterpret_cast<uintptr_t>(src) & 15) == 0 && s0 + VEC <= a.tw) {
             auto q = (const PLV_GLOBAL vf4 *)(src + s0);
             const vf4 q0 = q[0], q1 = q[1];
             zin[0] = vf2{q0.x, q0.y};

@@ -884,6 +884,188 @@ plv_status plv_coherence(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, 
     return enqueue_forward(ctx, plan, probs, nullptr, 1, 0.0, (uint8_t *)ws, (hipStream_t)stream);
 }
 
+// Coherency over windowed segments: the segment spectra go into the front of
+// the workspace, bin-major per problem, and every (problem, bin) becomes a
+// coherency problem over those coefficient rows (rows = signals, samples =
+// segments), planned behind them.
+struct StftPlan {
+    int nbins = 0;
+    size_t tw_off = 0, win_off = 0;
+    std::vector<int> nseg;          // per input problem
+    std::vector<size_t> coef_off;   // per input problem
+    std::vector<plv_problem> coh;   // per (problem, bin)
+    size_t coh_off = 0;             // the coherency plan's part of the workspace
+    Plan plan;
+    size_t total = 0;
+};
+
+static size_t align256_(size_t x) { return (x + 255) & ~size_t(255); }
+
+// base: the workspace (or any 256-byte aligned stand-in when only sizing)
+static plv_status stft_plan(const plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                            const plv_stft *st, uint8_t *base, StftPlan &sp, std::string &why)
+{
+    char b[256];
+    if ((int)prec < 0 || (int)prec > 4) {
+        why = "unknown precision";
+        return PLV_ERR_INVALID_ARG;
+    }
+    if (!st) {
+        why = "stft descriptor is NULL";
+        return PLV_ERR_INVALID_ARG;
+    }
+    if (st->seg < 2 || st->seg > STFT_MAX_SEG || st->hop < 1 || st->k_lo < 0 || st->k_hi < st->k_lo ||
+        st->k_hi > st->seg / 2 || st->k_hi - st->k_lo + 1 > 512 || st->window < 0 || st->window > 2 ||
+        st->reserved != 0) {
+        snprintf(b, sizeof b,
+                 "segmentation out of range: need 2 <= seg <= %d, hop >= 1, 0 <= k_lo <= k_hi <= seg/2, at most "
+                 "512 bins, a known window, reserved 0 (seg %d, hop %d, bins %d..%d, window %d)",
+                 STFT_MAX_SEG, st->seg, st->hop, st->k_lo, st->k_hi, st->window);
+        why = b;
+        return PLV_ERR_INVALID_ARG;
+    }
+    if (!probs || nprob < 1 || nprob > (1 << 20)) {
+        why = "need 1 <= nprob <= 2^20 problems and a non-NULL array";
+        return PLV_ERR_INVALID_ARG;
+    }
+    const bool f64 = prec == PLV_PREC_F64;
+    const size_t rsz = f64 ? 8 : 4, csz = 2 * rsz;
+    sp = StftPlan();
+    sp.nbins = st->k_hi - st->k_lo + 1;
+    size_t off = 0;
+    sp.tw_off = off;
+    off += align256_((size_t)st->seg * csz);
+    sp.win_off = off;
+    off += align256_((size_t)st->seg * rsz);
+    for (int64_t q = 0; q < nprob; ++q) {
+        const plv_problem &p = probs[q];
+        const int64_t t1 = p.t1 == 0 ? p.t : p.t1;
+        if (p.n < 1 || p.n > (1 << 20) || p.t < 1 || p.ld < p.t || p.t0 < 0 || t1 <= p.t0 || t1 > p.t || !p.in ||
+            reinterpret_cast<uintptr_t>(p.in) % rsz) {
+            snprintf(b, sizeof b,
+                     "problem %lld: need 1 <= n <= 2^20, t >= 1, ld >= t, 0 <= t0 < t1 <= t and %d-byte aligned "
+                     "input",
+                     (long long)q, (int)rsz);
+            why = b;
+            return PLV_ERR_INVALID_ARG;
+        }
+        if (t1 - p.t0 < st->seg) {
+            snprintf(b, sizeof b, "problem %lld: the window [t0, t1) holds %lld samples, less than one segment",
+                     (long long)q, (long long)(t1 - p.t0));
+            why = b;
+            return PLV_ERR_INVALID_ARG;
+        }
+        const int64_t S = (t1 - p.t0 - st->seg) / st->hop + 1;
+        if (S > (1 << 30)) {
+            why = "too many segments";
+            return PLV_ERR_INVALID_ARG;
+        }
+        sp.nseg.push_back((int)S);
+        sp.coef_off.push_back(off);
+        off += align256_((size_t)sp.nbins * p.n * S * csz);
+    }
+    const size_t esz = f64 ? 8 : 4;
+    for (int64_t q = 0; q < nprob; ++q) {
+        const plv_problem &p = probs[q];
+        const int S = sp.nseg[q];
+        const size_t nn = (size_t)p.n * (size_t)p.n;
+        for (int k = 0; k < sp.nbins; ++k) {
+            plv_problem d{};
+            d.n = p.n;
+            d.t = S;
+            d.ld = S;
+            d.in = base + sp.coef_off[q] + (size_t)k * p.n * S * csz;
+            d.plv = p.plv ? (uint8_t *)p.plv + k * nn * esz : nullptr;
+            d.iplv = p.iplv ? (uint8_t *)p.iplv + k * nn * esz : nullptr;
+            d.ciplv = p.ciplv ? (uint8_t *)p.ciplv + k * nn * esz : nullptr;
+            d.g = p.g ? (uint8_t *)p.g + 2 * k * nn * esz : nullptr;
+            sp.coh.push_back(d);
+        }
+    }
+    sp.coh_off = off;
+    plv_status r = make_plan(ctx ? ctx->cus : 256, ctx ? ctx->occ : nullptr, PLV_OP_COHERENCE, prec, sp.coh.data(),
+                             (int64_t)sp.coh.size(), nullptr, 1, sp.plan, why, ctx ? &ctx->tune : nullptr);
+    if (r != PLV_OK)
+        return r;
+    sp.total = off + sp.plan.total;
+    return PLV_OK;
+}
+
+plv_status plv_coherence_stft_workspace_size(const plv_ctx *ctx, plv_prec prec, const plv_problem *probs,
+                                             int64_t nprob, const plv_stft *stft, size_t *bytes)
+{
+    if (!bytes)
+        return PLV_ERR_INVALID_ARG;
+    *bytes = 0;
+    StftPlan sp;
+    std::string why;
+    const plv_status st = stft_plan(ctx, prec, probs, nprob, stft, (uint8_t *)(uintptr_t)256, sp, why);
+    if (st != PLV_OK) {
+        if (ctx)
+            const_cast<plv_ctx *>(ctx)->err = why;
+        return st;
+    }
+    *bytes = sp.total;
+    return PLV_OK;
+}
+
+plv_status plv_coherence_stft(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
+                              const plv_stft *stft, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!ctx)
+        return PLV_ERR_INVALID_ARG;
+    ctx->err.clear();
+    if (ctx->device < 0)
+        return fail(ctx, PLV_ERR_INVALID_ARG, "host-only context cannot compute");
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
+        return fail(ctx, PLV_ERR_WORKSPACE, "workspace must be non-NULL and 256-byte aligned");
+    StftPlan sp;
+    std::string why;
+    plv_status st = stft_plan(ctx, prec, probs, nprob, stft, (uint8_t *)ws, sp, why);
+    if (st != PLV_OK)
+        return fail(ctx, st, "%s", why.c_str());
+    if (ws_bytes < sp.total)
+        return fail(ctx, PLV_ERR_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, sp.total);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "hipSetDevice");
+    const hipStream_t s = (hipStream_t)stream;
+    const bool f64 = prec == PLV_PREC_F64;
+    uint8_t *w8 = (uint8_t *)ws;
+    {
+        StageTimer tm(ctx, PLV_STAGE_STFT, s);
+        StftTables tt{};
+        tt.seg = stft->seg;
+        tt.window = stft->window;
+        tt.tw = w8 + sp.tw_off;
+        tt.win = w8 + sp.win_off;
+        if ((e = launch_stft_tables(f64, tt, s)) != hipSuccess)
+            return hip_fail(ctx, e, "segment table kernel launch");
+        tm.launched();
+        for (int64_t q = 0; q < nprob; ++q) {
+            const plv_problem &p = probs[q];
+            StftArgs a{};
+            a.x = p.in;
+            a.ld = p.ld;
+            a.t0 = p.t0;
+            a.n = (int32_t)p.n;
+            a.seg = stft->seg;
+            a.hop = stft->hop;
+            a.nseg = sp.nseg[q];
+            a.k_lo = stft->k_lo;
+            a.k_hi = stft->k_hi;
+            a.spw = std::max(1, std::min(a.nseg, 256 / sp.nbins));
+            a.tw = tt.tw;
+            a.win = tt.win;
+            a.coef = w8 + sp.coef_off[q];
+            if ((e = launch_stft(f64, a, s)) != hipSuccess)
+                return hip_fail(ctx, e, "segment spectrum kernel launch");
+            tm.launched();
+        }
+    }
+    return enqueue_forward(ctx, sp.plan, sp.coh.data(), nullptr, 1, 0.0, w8 + sp.coh_off, s);
+}
+
 plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
                          const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes, void *stream)
 {

@@ -277,6 +277,27 @@ struct BwdNormArgs {        // zbar = i Im(conj(u) ubar) u / |z|
     int32_t row0;            // first row of this launch (rows run on blockIdx.y)
 };
 
+// ------------------------------------------------------ segment spectra --
+// Windowed-segment DFT bins for the coherency over segments (stft.hip).
+constexpr int STFT_MAX_SEG = 4096;   // longest segment (LDS-resident twiddles and window)
+
+struct StftTables {
+    int32_t seg, window;  // L, plv_window
+    void *tw;             // [L] complex exp(-2 pi i j / L) (R precision)
+    void *win;            // [L] window w[m] (R precision)
+};
+
+struct StftArgs {
+    const void *x;        // real rows [n][ld] (f32; f64 in F64 mode)
+    int64_t ld, t0;       // row stride, first sample of segment 0
+    int32_t n, seg, hop, nseg;
+    int32_t k_lo, k_hi;
+    int32_t spw;          // segments per work-group
+    int32_t row0;         // first row of this launch (rows run on blockIdx.y)
+    const void *tw, *win; // StftTables
+    void *coef;           // [k_hi - k_lo + 1][n][nseg] complex (c64; c128 in F64 mode)
+};
+
 // -------------------------------------------------------------- launchers --
 // Row-parallel launches put rows on gridDim.y, whose limit is 65535; the
 // launchers cover larger n in blocks of rows.
@@ -314,5 +335,7 @@ constexpr int SYNTH_S = 64, SYNTH_R = 256;  // samples and rows per band-synthes
 hipError_t launch_planes_t(int mode, const BwdPlanesArgs &a, hipStream_t s);
 hipError_t launch_metric_adjoint(int mode, const BwdMetricArgs &a, hipStream_t s);
 hipError_t launch_normalise_adjoint(bool f64, const BwdNormArgs &a, hipStream_t s);
+hipError_t launch_stft_tables(bool f64, const StftTables &a, hipStream_t s);
+hipError_t launch_stft(bool f64, const StftArgs &a, hipStream_t s);
 
 }  // namespace plv
