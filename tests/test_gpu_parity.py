@@ -164,16 +164,20 @@ def test_grouped_batch_equals_single_calls(prec):
 @pytest.mark.parametrize("prec", ["split_bf16", "f32"])
 def test_sensor_scale_workload_sampled_pairs(prec):
     """N = 1024 analytic signals of T = 60000 samples (1 kHz, 60 s), 32 latent
-    8-12 Hz oscillators: the full-size workload, checked on sampled pairs (the
-    oracle computes them one by one) and on properties of every entry."""
+    8-12 Hz oscillators: the full-size workload, in the launch configuration
+    the benchmark times.  Every pair among 256 rows -- four from each 16-row
+    block, so every 16 x 16 MFMA block of every 128 x 128 tile holds 16
+    checked entries -- against the oracle (which computes pairs one by one),
+    plus every zero-lag-mixed neighbour pair (2m, 2m+1) of the first 200
+    rows; then a bilinear probe per tile and properties of every entry."""
     n, t = 1024, 60000
     z = synth.glag_analytic(n, t, 1000.0, 32, (8.0, 12.0), seed=synth.seed_for(2), dtype=np.complex64)
     got = gpu_full(z, prec)
     rng = np.random.default_rng(5)
-    # sampled pairs: random ones plus every zero-lag-mixed neighbour pair (2m, 2m+1)
-    pr = np.concatenate([rng.integers(0, n, size=(600, 2)),
+    rows = np.sort(np.concatenate([16 * q + rng.choice(16, size=4, replace=False) for q in range(n // 16)]))
+    ii, jj = np.triu_indices(len(rows), 1)
+    pr = np.concatenate([np.stack([rows[ii], rows[jj]], 1),
                          np.stack([np.arange(0, 200, 2), np.arange(1, 200, 2)], 1)])
-    pr = pr[pr[:, 0] != pr[:, 1]]
     g = oracle.pairs_from_analytic(z.astype(np.complex128), pr)
     p, ip, cp = oracle.metrics(g)
     a, b = pr[:, 0], pr[:, 1]
@@ -189,13 +193,41 @@ def test_sensor_scale_workload_sampled_pairs(prec):
     assert np.array_equal(got["plv"], got["plv"].T)
     assert got["plv"].max() <= 1.0 + 1e-5 and got["plv"].min() >= 0.0
     assert abs(np.trace(got["g"]).real - n) <= n * tol
-    # a probe vector w: w^H G w = ||U^H w||^2 / T for the exact phasors
+    # per tile (I, J): with unit-modulus weights w on the rows of panel I and
+    # v on those of panel J, sum_ij conj(w_i) G_ij v_j = (1/T) sum_t a(t) b(t),
+    # a = sum_i conj(w_i) u_i, b = sum_j v_j conj(u_j) over the exact phasors;
+    # each of the tile's 128^2 entries is within tol, hence the bound
     u = z.astype(np.complex128)
     u = u / np.abs(u)
-    w = rng.standard_normal(n) + 1j * rng.standard_normal(n)
-    lhs = np.vdot(w, got["g"] @ w).real
-    rhs = np.linalg.norm(u.conj().T @ w) ** 2 / t
-    assert abs(lhs - rhs) <= tol * np.abs(w).sum() ** 2
+    bm = 128
+    for I in range(n // bm):
+        for J in range(I, n // bm):
+            w = np.exp(2j * np.pi * rng.random(bm))
+            v = np.exp(2j * np.pi * rng.random(bm))
+            ra, rb = slice(I * bm, (I + 1) * bm), slice(J * bm, (J + 1) * bm)
+            lhs = np.conj(w) @ got["g"][ra, rb] @ v
+            rhs = np.sum((np.conj(w) @ u[ra]) * (v @ np.conj(u[rb]))) / t
+            assert abs(lhs - rhs) <= 2 * tol * bm * bm, (I, J)
+
+
+def test_input_rows_off_a_16_byte_boundary():
+    """A z[:, 1:] view: every row starts 8 bytes past a 16-byte boundary, so
+    the normalisation must take its per-sample loads, with the same result
+    as a contiguous copy and the oracle."""
+    n, t = 70, 1001
+    z = synth.glag_analytic(n, t + 1, 1000.0, 8, (8.0, 12.0), seed=synth.seed_for(2, 40), dtype=np.complex64)
+    zd = torch.from_numpy(z).cuda()
+    view = zd[:, 1:]
+    assert view.data_ptr() % 16 == 8 and view.stride(0) == t + 1
+    for prec in ("split_bf16", "f32"):
+        got = plv_mod().from_analytic(view, prec=prec, want_g=True)
+        ref = plv_mod().from_analytic(view.contiguous(), prec=prec, want_g=True)
+        torch.cuda.synchronize()
+        for k in ("plv", "iplv", "ciplv", "g"):
+            assert torch.equal(got[k], ref[k]), (prec, k)
+        o = oracle.full_from_analytic(exact_input(z[:, 1:], prec))
+        h = {k: v.cpu().numpy().astype(np.complex128 if k == "g" else np.float64) for k, v in got.items()}
+        compare(h, o, TOL[prec], "offset view %s" % prec)
 
 
 @pytest.mark.parametrize("prec", ["f32", "split_bf16", "f64"])
