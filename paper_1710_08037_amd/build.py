@@ -27,6 +27,7 @@ SOURCES = [
     "fft.hip",
     "backward.hip",
     "stft.hip",
+    "dft.hip",
 ]
 
 CFLAGS = [

@@ -430,15 +430,22 @@ static bool direct_band(const FftPlan &f, BandBins bb)
 
 // Host tables of the FFT stage in the upload blob: problems, band bins, rows
 // grouped by FFT size (class_start / class_count per size), per-length jobs.
+// A problem whose bands are all synthesised from their bins, with at most
+// DFT_MAX_BINS bins in all, takes them from the DFT-bins kernel (an MFMA
+// product with the row) rather than a whole transform of the row (forward
+// calls in the FP32 modes).  Its rows stay out of the transform launches.
 static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const plv_grad *grads,
                             const plv_band *bands, int nbands, double fs, uint8_t *ws, std::vector<uint8_t> &blob,
                             std::vector<int> &class_start, std::vector<int> &class_count, bool &any_direct,
-                            int64_t &synth_jobs)
+                            int64_t &synth_jobs, int64_t &dft_jobs)
 {
     any_direct = false;
     synth_jobs = 0;
+    dft_jobs = 0;
     const bool backward = plan.op == PLV_OP_BACKWARD_REAL;
     int32_t *prefix = (int32_t *)(blob.data() + plan.synth_off);
+    int32_t *dprefix = (int32_t *)(blob.data() + plan.dftp_off);
+    std::vector<char> by_dft(plan.fft.size(), 0);
     const size_t nprob = plan.fft.size();
     HilbertProb *hp = (HilbertProb *)(blob.data() + plan.hp_off);
     BandBins *bins = (BandBins *)(blob.data() + plan.bin_off);
@@ -480,6 +487,17 @@ static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const pl
             any_direct = any_direct || bb.direct;
             bins[q * nbands + b] = bb;
         }
+        int kt = 0;
+        bool all_direct = !backward && plan.mode != M_F64;
+        for (int b = 0; b < nbands; ++b) {
+            const BandBins &bb = bins[q * nbands + b];
+            all_direct = all_direct && bb.direct;
+            kt += bb.khi >= bb.klo ? bb.khi - bb.klo + 1 : 0;
+        }
+        by_dft[q] = all_direct && kt <= DFT_MAX_BINS;
+        dprefix[q] = (int32_t)std::min<int64_t>(dft_jobs, INT32_MAX);
+        if (by_dft[q])
+            dft_jobs += (p.n + DFT_ROWS_PER_WG - 1) / DFT_ROWS_PER_WG;
         // band synthesis work-groups of this problem (band_synth_kernel's decode)
         const GramPlan &g0 = plan.grams[q * nbands];
         const int64_t len = backward ? g0.t : g0.tpad;
@@ -487,11 +505,12 @@ static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const pl
         synth_jobs += (int64_t)nbands * ((len + SYNTH_S - 1) / SYNTH_S) * ((p.n + SYNTH_R - 1) / SYNTH_R);
     }
     prefix[nprob] = (int32_t)std::min<int64_t>(synth_jobs, INT32_MAX);
+    dprefix[nprob] = (int32_t)std::min<int64_t>(dft_jobs, INT32_MAX);
     size_t r = 0;
     for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
         class_start.push_back((int)r);
         for (size_t q = 0; q < nprob; ++q)
-            if (plan.fft[q].logm == plan.tw_logm[c])
+            if (plan.fft[q].logm == plan.tw_logm[c] && !by_dft[q])
                 for (int64_t i = 0; i < probs[q].n; ++i)
                     rows[r++] = RowRef{(int32_t)q, (int32_t)i};
         class_count.push_back((int)r - class_start.back());
@@ -571,6 +590,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
     std::vector<int> class_start, class_count;  // FFT rows per size class
     bool any_direct = false;                    // some band synthesised from its bins
     int64_t synth_jobs = 0;                     // its work-groups
+    int64_t dft_jobs = 0;                       // work-groups of the DFT-bins kernel
     if (plan.grouped || real) {
         std::vector<uint8_t> blob(plan.tables_bytes, 0);
         memcpy(blob.data() + plan.desc_off, gd.data(), gd.size() * sizeof(GramDesc));
@@ -580,7 +600,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
         }
         if (real)
             fill_fft_tables(plan, probs, nullptr, bands, nbands, fs, ws, blob, class_start, class_count, any_direct,
-                            synth_jobs);
+                            synth_jobs, dft_jobs);
         plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
         if (st != PLV_OK)
             return st;
@@ -594,6 +614,8 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             return hip_fail(ctx, e, "FFT set-up kernel launch");
         tm.launched(nl);
         for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+            if (class_count[c] == 0)
+                continue;  // every row of this size takes the DFT-bins kernel
             HilbertArgs ha{};
             ha.hp = (const HilbertProb *)(ws + plan.hp_off);
             ha.bins = (const BandBins *)(ws + plan.bin_off);
@@ -605,6 +627,19 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             ha.fir = plan.nfirjobs > 0 ? 1 : 0;
             if ((e = launch_hilbert(mode, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal kernel launch");
+            tm.launched();
+        }
+        if (dft_jobs > 0) {
+            if (dft_jobs >= INT32_MAX)
+                return fail(ctx, PLV_ERR_UNSUPPORTED, "DFT bins need %lld work-groups", (long long)dft_jobs);
+            HilbertArgs ha{};
+            ha.hp = (const HilbertProb *)(ws + plan.hp_off);
+            ha.bins = (const BandBins *)(ws + plan.bin_off);
+            ha.nbands = nbands;
+            ha.nprob = (int32_t)plan.fft.size();
+            ha.dft_prefix = (const int32_t *)(ws + plan.dftp_off);
+            if ((e = launch_dft_bins(ha, (int)dft_jobs, s)) != hipSuccess)
+                return hip_fail(ctx, e, "DFT bins kernel launch");
             tm.launched();
         }
         if (any_direct) {
@@ -1112,9 +1147,10 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
         memcpy(blob.data() + plan.desc_off, gd.data(), gd.size() * sizeof(GramDesc));
         if (plan.grouped)
             memcpy(blob.data() + plan.item_off, items.data(), items.size() * sizeof(Item));
+        int64_t dft_jobs = 0;  // (0: the backward takes every row through the transform)
         if (real)
             fill_fft_tables(plan, probs, grads, bands, nbands, fs, ws, blob, class_start, class_count, any_direct,
-                            synth_jobs);
+                            synth_jobs, dft_jobs);
         plv_status st = upload(ctx, blob, ws + plan.tables_off, s);
         if (st != PLV_OK)
             return st;

@@ -232,6 +232,7 @@ struct HilbertArgs {
     const int32_t *synth_prefix;  //   [nprob + 1] of the problems (see band_synth_kernel)
     int32_t fir;          // some band of the call is an FIR band (selects the kernel variant)
     int32_t pad2_;
+    const int32_t *dft_prefix;    // DFT-bins kernel: [nprob + 1] running work-group counts
 };
 
 // Set-up for one distinct row length t: its root table, and for a Bluestein
@@ -332,6 +333,12 @@ hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int cus, hipSt
 // their bins in HilbertProb::xbins; njobs = a.synth_prefix[a.nprob] work-groups
 hipError_t launch_band_synth(int mode, const HilbertArgs &a, int njobs, hipStream_t s);
 constexpr int SYNTH_S = 64, SYNTH_R = 256;  // samples and rows per band-synthesis work-group
+// Problems whose bands are all narrow, with at most DFT_MAX_BINS bins in all,
+// take their bins from the DFT-bins kernel (dft.hip, FP32 modes) instead of
+// the transform kernel; njobs = a.dft_prefix[a.nprob] work-groups of 64 rows.
+constexpr int DFT_MAX_BINS = 128;
+constexpr int DFT_ROWS_PER_WG = 64;
+hipError_t launch_dft_bins(const HilbertArgs &a, int njobs, hipStream_t s);
 hipError_t launch_planes_t(int mode, const BwdPlanesArgs &a, hipStream_t s);
 hipError_t launch_metric_adjoint(int mode, const BwdMetricArgs &a, hipStream_t s);
 hipError_t launch_normalise_adjoint(bool f64, const BwdNormArgs &a, hipStream_t s);

@@ -410,6 +410,8 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
         off += align256(plan.lens.size() * sizeof(ChirpJob));
         plan.synth_off = off;
         off += align256((size_t)(nprob + 1) * sizeof(int32_t));
+        plan.dftp_off = off;
+        off += align256((size_t)(nprob + 1) * sizeof(int32_t));
         // FIR bands: the taps' autocorrelation per band, and one weight-table
         // job per (row length, band); the tables themselves follow below
         std::vector<int> fir_bands;

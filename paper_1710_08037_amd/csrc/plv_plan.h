@@ -78,6 +78,7 @@ struct Plan {
     std::vector<LenPlan> lens;                // distinct row lengths, ordered by (logm, t)
     size_t hp_off = 0, bin_off = 0, row_off = 0, job_off = 0;
     size_t synth_off = 0;  // band synthesis: running work-group counts [nprob + 1]
+    size_t dftp_off = 0;   // DFT-bins kernel: running work-group counts [nprob + 1]
     std::vector<size_t> fir_r_off;  // per band: the FIR taps' autocorrelation (FP64, in the tables)
     size_t firjob_off = 0;          // FirJob per (row length, FIR band), in the tables
     int nfirjobs = 0, fir_max_t = 0;

@@ -177,3 +177,25 @@ def test_band_needs_sampling_rate():
     x = real_dev(synth.glag_real(4, 64, 100.0, 2, 10.0, seed=1), "f32")
     with pytest.raises(PLVError):
         plv_mod().from_real(x, 0.0, bands=[(8.0, 12.0)], prec="f32")
+
+
+@pytest.mark.parametrize("prec", ["f32", "split_bf16"])
+def test_dft_bins_path_edge_cases(prec):
+    """Problems whose bands are all narrow take their bins from the MFMA DFT
+    kernel instead of a transform: rows shorter than one 64-sample chunk and
+    ragged in T, row counts off the 64-row work-group and 16-row MFMA blocks,
+    an empty band, a single-bin band, T at the 4096-sample limit of the
+    path's lengths, and a window; all against the oracle."""
+    fs = 1000.0
+    bands = [(8.0, 12.0), (30.0, 34.0), (0.4, 0.6), (100.0, 100.0)]
+    shapes = [(5, 37), (70, 130), (17, 1000), (129, 4096), (64, 3001)]
+    xs = [synth.glag_real(n, t, fs, 4, (5.0, 40.0), seed=700 + k) for k, (n, t) in enumerate(shapes)]
+    wins = [None, (10, 120), None, (100, 4000), (1, 3000)]
+    outs = plv_mod().from_real_batch([real_dev(x, prec) for x in xs], fs, bands=bands, prec=prec, want_g=True,
+                                     windows=[w if w else (0, x.shape[1]) for w, x in zip(wins, xs)])
+    torch.cuda.synchronize()
+    for k, x in enumerate(xs):
+        xr = exact_real(x, prec)
+        for b, band in enumerate(bands):
+            ref = oracle.full_from_real(xr, fs, band, window=wins[k])
+            compare(to_np(outs[k], b), ref, TOL[prec], "problem %d band %d" % (k, b))
