@@ -92,15 +92,21 @@ __global__ __launch_bounds__(256) void dft_bins_kernel(HilbertArgs a)
     for (int c0 = 0; c0 < t; c0 += DFT_TC) {
         __syncthreads();  // the previous chunk's columns are read
         if (wj < nkt) {
+            // all RUN gathers in flight at once, then the LDS writes
             const int s0 = c0 + wq * RUN;
-            int idx = (int)(((int64_t)kj * s0) % t);
+            uint32_t idx = ((uint32_t)kj * (uint32_t)s0) % (uint32_t)t;  // < 2^31: k <= t/2, s0 < t
+            vf2 rv[RUN];
+#pragma unroll
             for (int u = 0; u < RUN; ++u) {
-                const vf2 r = gptr(roots)[idx];
+                rv[u] = gptr(roots)[idx];
+                idx += (uint32_t)kj;
+                idx = idx >= (uint32_t)t ? idx - (uint32_t)t : idx;
+            }
+#pragma unroll
+            for (int u = 0; u < RUN; ++u) {
                 const bool in = s0 + u < t;
-                wt[2 * wj][wq * RUN + u] = in ? r.x : 0.0f;        // Re W = cos
-                wt[2 * wj + 1][wq * RUN + u] = in ? -r.y : 0.0f;   // Im W = -sin
-                idx += kj;
-                idx = idx >= t ? idx - t : idx;
+                wt[2 * wj][wq * RUN + u] = in ? rv[u].x : 0.0f;        // Re W = cos
+                wt[2 * wj + 1][wq * RUN + u] = in ? -rv[u].y : 0.0f;   // Im W = -sin
             }
         }
         __syncthreads();

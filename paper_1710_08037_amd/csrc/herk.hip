@@ -413,6 +413,66 @@ __device__ inline void fold_groups(typename AccOf<MODE>::type (&re)[BM / 32][BM 
     }
 }
 
+// Fused store of a single-chunk tile (I, J): the measures (and G) of its
+// upper-triangle entries at (i, j) and their mirror at (j, i), both written
+// row by row.  Group 0's accumulators (after the fold) go to LDS as two
+// BM x BM planes (Re, Im) of the accumulator type, the column of element
+// (a, b) XOR-swizzled by a mod 64, so that reading a row (the block at rows
+// of I) and reading a column (the mirrored block at rows of J) both spread
+// over the banks.  Then all 8 waves store: consecutive threads take
+// consecutive columns of one output row, every store a contiguous run.
+template <int MODE, int BM>
+__device__ inline void fused_store(const GramDesc &d, int I, int J,
+                                   typename AccOf<MODE>::type (&re)[BM / 32][BM / 32],
+                                   typename AccOf<MODE>::type (&im)[BM / 32][BM / 32], uint8_t *smem)
+{
+    constexpr int NB = BM / 32;
+    typedef typename std::conditional<MODE == M_F64, double, float>::type acc_e;
+    static_assert(2 * BM * BM * (int)sizeof(acc_e) <= Ring<MODE, BM>::NS * Ring<MODE, BM>::STAGE,
+                  "the ring holds the tile");
+    acc_e *tr = (acc_e *)smem, *ti = tr + BM * BM;
+    auto at = [](int a, int b) { return a * BM + (b ^ (a & 63)); };
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();  // the fold's reads of the ring are done
+    if (wave < 4) {
+        const int wm = wave >> 1, wn = wave & 1;
+        const int r0 = wm * (BM / 2) + (MODE == M_F64 ? (lane >> 4) : (lane >> 4) * 4);
+        constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;
+        const int c0 = wn * (BM / 2) + (lane & 15);
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int e = at(r0 + a * 16 + r * RSTEP, c0 + b * 16);
+                    tr[e] = re[a][b][r];
+                    ti[e] = im[a][b][r];
+                }
+    }
+    __syncthreads();
+    const double inv_t = 1.0 / (double)d.t;
+    const int64_t n = d.n;
+    constexpr int LBM = BM == 128 ? 7 : 6;
+    // block 0: rows of I, columns of J, entry (a, b) as accumulated;
+    // block 1: rows of J, columns of I, entry (a, b) the conjugate of (b, a)
+    // (one code path for both blocks: an entry and its mirror are computed
+    // by the same instructions from the same values)
+#pragma unroll 1
+    for (int blk = 0; blk < 2; ++blk) {
+        const int64_t row0 = (int64_t)(blk ? J : I) * BM, col0 = (int64_t)(blk ? I : J) * BM;
+        for (int e = threadIdx.x; e < BM * BM; e += THREADS) {
+            const int a = e >> LBM, b = e & (BM - 1);
+            const int64_t gr = row0 + a, gc = col0 + b;
+            if (gr >= n || gc >= n || (blk ? gc >= gr : gr > gc))
+                continue;
+            const int s = blk ? at(b, a) : at(a, b);
+            const double vr = (double)tr[s] * inv_t, vi = (double)ti[s] * inv_t;
+            store_one<MODE>(d, gr * n + gc, gr == gc, blk != 0, vr, vi);
+        }
+    }
+}
+
 // Work-groups per CU the launch bounds ask for: the 64-wide tile of the
 // 16-bit and FP32 modes takes half the LDS ring and a quarter of the
 // accumulators, so two work-groups share a CU.
@@ -482,6 +542,10 @@ __global__ __launch_bounds__(THREADS, (wg_per_cu<MODE, BM>())) void herk_kernel(
     fold_groups<MODE, BM>(re, im, smem);
 
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (d.fused && !d.ub) {
+        fused_store<MODE, BM>(d, I, J, re, im, smem);
+        return;
+    }
     if (wave >= 4)
         return;
     const int wm = wave >> 1, wn = wave & 1;
@@ -506,25 +570,6 @@ __global__ __launch_bounds__(THREADS, (wg_per_cu<MODE, BM>())) void herk_kernel(
                         v.y = im[a][b][r];
                         cp[i * d.ldc + j] = v;
                     }
-                }
-        return;
-    }
-    if (d.fused) {
-        // ---- single chunk: the measures straight from the accumulators
-        const double inv_t = 1.0 / (double)d.t;
-        const int r0 = wm * (BM / 2) + (MODE == M_F64 ? (lane >> 4) : (lane >> 4) * 4);
-        constexpr int RSTEP = (MODE == M_F64) ? 4 : 1;
-        const int c0 = wn * (BM / 2) + (lane & 15);
-#pragma unroll
-        for (int a = 0; a < NB; ++a)
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t gi = (int64_t)I * BM + r0 + a * 16 + r * RSTEP;
-                    const int64_t gj = (int64_t)J * BM + c0 + b * 16;
-                    if (gi < d.n && gj < d.n && gi <= gj)
-                        store_entry<MODE>(d, gi, gj, (double)re[a][b][r] * inv_t, (double)im[a][b][r] * inv_t);
                 }
         return;
     }

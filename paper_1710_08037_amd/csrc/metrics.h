@@ -27,17 +27,13 @@ struct OutT {
     typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
 };
 
-// Off-diagonal entry: r, m are Re and Im of G_ij (already divided by T),
-// ij and ji the flat indices of (i, j) and (j, i).
+// The three measures of an off-diagonal entry from r, m = Re and Im of G_ij
+// (already divided by T).
 template <int MODE>
-__device__ inline void store_pair(const GramDesc &d, int64_t ij, int64_t ji, double r, double m)
+__device__ inline void measures(double r, double m, typename OutT<MODE>::real_t &vp, typename OutT<MODE>::real_t &vi,
+                                typename OutT<MODE>::real_t &vc)
 {
-    typedef typename OutT<MODE>::real_t real_t;
-    typedef typename OutT<MODE>::cplx_t cplx_t;
-    auto plv = gptr((real_t *)d.plv), iplv = gptr((real_t *)d.iplv), ciplv = gptr((real_t *)d.ciplv);
-    auto g = gptr((cplx_t *)d.g);
     const double dd = (1.0 - r) * (1.0 + r);  // FP64: 1 - Re cancels
-    real_t vp, vi, vc;
     if constexpr (MODE == M_F64) {
         const double am = fabs(m);
         vp = sqrt(r * r + m * m);
@@ -57,6 +53,19 @@ __device__ inline void store_pair(const GramDesc &d, int64_t ij, int64_t ji, dou
         vi = am;
         vc = dd > 0.0 ? (am * sc) * __builtin_amdgcn_rsqf((float)dd) * isc : 0.0f;
     }
+}
+
+// Off-diagonal entry: r, m are Re and Im of G_ij (already divided by T),
+// ij and ji the flat indices of (i, j) and (j, i).
+template <int MODE>
+__device__ inline void store_pair(const GramDesc &d, int64_t ij, int64_t ji, double r, double m)
+{
+    typedef typename OutT<MODE>::real_t real_t;
+    typedef typename OutT<MODE>::cplx_t cplx_t;
+    auto plv = gptr((real_t *)d.plv), iplv = gptr((real_t *)d.iplv), ciplv = gptr((real_t *)d.ciplv);
+    auto g = gptr((cplx_t *)d.g);
+    real_t vp, vi, vc;
+    measures<MODE>(r, m, vp, vi, vc);
     if (plv) {
         plv[ij] = vp;
         plv[ji] = vp;
@@ -76,6 +85,35 @@ __device__ inline void store_pair(const GramDesc &d, int64_t ij, int64_t ji, dou
         g[ij] = v;
         v.y = (real_t)(-m);
         g[ji] = v;
+    }
+}
+
+// One entry only, no mirror: the measures of G (r, m = Re and Im of the
+// upper-triangle entry, already divided by T), or the diagonal's 1 / 0 / 0;
+// G as given, or its conjugate when `conj` (the mirrored entry).  The
+// measures never see the sign of m, so an entry and its mirror get
+// bit-identical values from the same (r, m).
+template <int MODE>
+__device__ inline void store_one(const GramDesc &d, int64_t idx, bool diag, bool conj, double r, double m)
+{
+    typedef typename OutT<MODE>::real_t real_t;
+    typedef typename OutT<MODE>::cplx_t cplx_t;
+    auto plv = gptr((real_t *)d.plv), iplv = gptr((real_t *)d.iplv), ciplv = gptr((real_t *)d.ciplv);
+    auto g = gptr((cplx_t *)d.g);
+    real_t vp = (real_t)1, vi = (real_t)0, vc = (real_t)0;
+    if (!diag)
+        measures<MODE>(r, m, vp, vi, vc);
+    if (plv)
+        plv[idx] = vp;
+    if (iplv)
+        iplv[idx] = vi;
+    if (ciplv)
+        ciplv[idx] = vc;
+    if (g) {
+        cplx_t v;
+        v.x = (real_t)r;
+        v.y = conj ? (real_t)(-m) : (real_t)m;
+        g[idx] = v;
     }
 }
 
