@@ -530,7 +530,7 @@ __global__ __launch_bounds__(256) void band_synth_kernel(HilbertArgs a, int mode
 // FIR: the call has forward-backward FIR bands (weights from tables); the
 // variant without them keeps the mask path's registers.
 template <class R, int LOGM, bool FIR>
-__global__ __launch_bounds__(nt_of(LOGM)) __attribute__((amdgpu_waves_per_eu((LOGM == 12 || LOGM == 11) ? 4 : 1))) void hilbert_kernel(HilbertArgs a, int mode)
+__global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int mode)
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
     __shared__ cx<R> buf[buf_elems(LOGM)];
