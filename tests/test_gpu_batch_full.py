@@ -1,12 +1,12 @@
 """The uneven batch at its full size, in the launch configuration bench.py
 times: 512 trials (N in {68, 148, 360, 1000}, T uniform in [500, 4000] at
-1 kHz), five 4 Hz bands, real FP32 input, split-BF16 -- one call, one
-grouped Gram launch.  The same seeded inputs as the benchmark.
+1 kHz), five 4 Hz bands, real FP32 input, split-BF16 and plain BF16 -- one
+call, one grouped Gram launch.  The same seeded inputs as the benchmark.
 
 Checked against the FP64 oracle on sampled outputs: for trials chosen to
 cover every N and every transform size class (plain and Bluestein lengths up
 to M = 8192), all pairs among sampled rows (first, last and random rows) in
-every band, to the split-BF16 tolerance of the other parity tests.  The
+every band, to each precision's tolerance in the other parity tests.  The
 analytic signal is per row, so the oracle needs only those rows.
 """
 import numpy as np
@@ -37,7 +37,8 @@ def compare_metrics(got, ref, tol, where):
         assert np.array_equal(got[k], got[k].T), k
 
 
-def test_uneven_batch_full_size_sampled():
+@pytest.mark.parametrize("prec", ["split_bf16", "bf16"])
+def test_uneven_batch_full_size_sampled(prec):
     import paper_1710_08037_amd as plv
     fs = 1000.0
     seed = synth.seed_for(4)
@@ -45,8 +46,8 @@ def test_uneven_batch_full_size_sampled():
     xs = [synth.glag_real(n, t, fs, 32, (2.0, 42.0), seed=seed + 1 + k, dtype=np.float32)
           for k, (n, t) in enumerate(shapes)]
     bands = synth.bands_hz()
-    print("uneven batch: 512 trials, from_real_batch split_bf16", flush=True)
-    outs = plv.from_real_batch([torch.from_numpy(x).cuda() for x in xs], fs, bands=bands, prec="split_bf16")
+    print("uneven batch: 512 trials, from_real_batch", prec, flush=True)
+    outs = plv.from_real_batch([torch.from_numpy(x).cuda() for x in xs], fs, bands=bands, prec=prec)
     torch.cuda.synchronize()
 
     # trials: for each N, the shortest, median and longest T
@@ -69,4 +70,4 @@ def test_uneven_batch_full_size_sampled():
             ref = oracle.full_from_real(xr, fs, band)
             got = {m: outs[k][m][b].cpu().numpy().astype(np.float64)[np.ix_(rows, rows)]
                    for m in ("plv", "iplv", "ciplv")}
-            compare_metrics(got, ref, TOL["split_bf16"], "trial %d (N=%d T=%d) band %d" % (k, n, t, b))
+            compare_metrics(got, ref, TOL[prec], "trial %d (N=%d T=%d) band %d" % (k, n, t, b))
