@@ -215,9 +215,8 @@ plv_status plv_from_analytic(plv_ctx *ctx, plv_prec prec, const plv_problem *pro
  * with nbands = 1 for the plain analytic signal.  fs > 0 is the sampling rate
  * in Hz used to place band edges (ignored when every band is plain).
  * A row's transforms are held in LDS: the FFT size M (t for a power-of-two
- * t >= 2, else the power of two >= 2t - 1) must be <= 8192 in the FP32 / BF16
- * / FP16 modes and <= 4096 in PLV_PREC_F64; longer rows return
- * PLV_ERR_UNSUPPORTED. */
+ * t >= 2, else the power of two >= 2t - 1) must be <= 8192 in every mode;
+ * longer rows return PLV_ERR_UNSUPPORTED. */
 plv_status plv_from_real(plv_ctx *ctx, plv_prec prec, const plv_problem *probs, int64_t nprob,
                          const plv_band *bands, int32_t nbands, double fs, void *ws, size_t ws_bytes,
                          void *stream);

@@ -23,8 +23,11 @@
 // LDS, built once per work-group from the quarter-wave table
 // exp(-2 pi i m / M), m < M/4, by exact rotations.
 //
-// Bands: X stays in registers (and in LDS) after the forward transform.  A
-// band whose bin count K is small relative to the FFT cost is synthesised
+// Bands: X stays in LDS after the forward transform; the first band taking the
+// inverse transform reads it there, and when more follow (which overwrite
+// the LDS) X is first copied to a slot of the work-group in global memory, so
+// that no second M-element array is held in registers.  A band whose bin
+// count K is small relative to the FFT cost is synthesised
 // directly, z(n) = (2/t) sum_{k=klo..khi} X_k exp(2 pi i k n / t), as
 // exp(2 pi i klo n / t) times a Horner polynomial in exp(2 pi i n / t) read
 // from a per-length root table; other bands (and the plain analytic signal)
@@ -83,6 +86,20 @@ __device__ inline void gst(cx<R> *p, int64_t i, cx<R> a)
     gptr((v2_t<R> *)p)[i] = v2_t<R>{a.x, a.y};
 }
 
+// The same pointer (one value in every lane), opaque to the optimiser and
+// held in scalar registers: addresses formed from it are recomputed where
+// they are used instead of being hoisted out of the row and band loops and
+// held in vector registers across the transforms.
+template <class T>
+__device__ inline T *fresh(T *p)
+{
+    const uint64_t u = (uint64_t)(uintptr_t)p;
+    uint64_t w = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(u >> 32)) << 32) |
+                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    asm volatile("" : "+s"(w));
+    return (T *)(uintptr_t)w;
+}
+
 // ------------------------------------------------------------ shapes --
 #ifndef PLV_FFT_LP
 #define PLV_FFT_LP 3
@@ -107,6 +124,13 @@ __host__ __device__ constexpr int ptab_elems(int logm)
 {
     return npass_of(logm) <= 1 ? 1 : ptab_off(logm, npass_of(logm) - 1) + ptab_len(logm, npass_of(logm) - 1);
 }
+// FP64 at M = 8192: the sequence alone takes 136 KB of LDS, so the passes read
+// their twiddles straight from the quarter-wave table in global memory (32 KB,
+// cache-resident; the same values the LDS tables would hold).
+template <class R>
+__host__ __device__ constexpr bool gtw_of(int logm) { return sizeof(R) == 8 && logm >= 13; }
+template <class R>
+__host__ __device__ constexpr int ptab_lds_elems(int logm) { return gtw_of<R>(logm) ? 1 : ptab_elems(logm); }
 
 // a * exp(-+2 pi i m / 16) (forward: minus), m a constant after unrolling.
 template <class R, bool INV>
@@ -204,6 +228,19 @@ __device__ inline cx<R> twiddle(const cx<R> *twq, int idx)
     return o;
 }
 
+// The same from the quarter-wave table in global memory.
+template <class R, int LOGM>
+__device__ inline cx<R> gtwiddle(const cx<R> *twq, int idx)
+{
+    constexpr int Q = LOGM - 2;
+    const int q = idx >> Q;
+    const cx<R> w = gld(twq, idx & ((1 << Q) - 1));
+    cx<R> o = (q & 1) ? cx<R>{w.y, -w.x} : w;
+    if (q & 2)
+        o = cx<R>{-o.x, -o.y};
+    return o;
+}
+
 // LDS index of element tid + e NTA (the natural register pattern); a base
 // plus constants when NTA is a multiple of 16.
 template <int LOGM>
@@ -246,7 +283,9 @@ __device__ inline void fft_pass(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R
                 const cx<R> *tw = ptab + ptab_off(LOGM, P) + kk * (RR - 1) - 1;
 #pragma unroll
                 for (int r = 1; r < RR; ++r) {
-                    const cx<R> w = tw[r];
+                    // W_(NS RR)^(r kk) = W_M^((r kk) M / (NS RR))
+                    const cx<R> w = gtw_of<R>(LOGM) ? gtwiddle<R, LOGM>(ptab, (r * kk) << (LOGM - LP * P - LR))
+                                                    : tw[r];
                     b[r] = cmul(b[r], INV ? cconj(w) : w);
                 }
             }
@@ -254,6 +293,9 @@ __device__ inline void fft_pass(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R
 #pragma unroll
             for (int r = 0; r < RR; ++r)
                 v[q + r * BPT] = b[r];
+            // one butterfly at a time: interleaving them only raises register use
+            if constexpr (BPT > 1)
+                __builtin_amdgcn_sched_barrier(0);
         }
     }
     __syncthreads();  // every thread has read this pass's input
@@ -278,7 +320,8 @@ __device__ inline void fft_pass(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R
 
 // Transform of the sequence held in v (natural pattern); the result is left
 // in buf in natural order (index lpad(k)), visible to the whole work-group.
-// Every thread of the work-group must call it.
+// ptab: the LDS pass tables, or the global quarter-wave table when
+// gtw_of<R>(LOGM).  Every thread of the work-group must call it.
 template <class R, int LOGM, bool INV>
 __device__ inline void fft_lds(cx<R> (&v)[per_of(LOGM)], cx<R> *buf, const cx<R> *ptab, bool act)
 {
@@ -307,7 +350,7 @@ template <class R, int LOGM>
 __device__ inline void build_tables(cx<R> *ptab, cx<R> *scratch, const void *tw_tab)
 {
     constexpr int M = 1 << LOGM, NP = npass_of(LOGM);
-    if constexpr (NP > 1) {
+    if constexpr (NP > 1 && !gtw_of<R>(LOGM)) {
         for (int k = threadIdx.x; k < M / 4; k += blockDim.x)
             scratch[k] = gld((const cx<R> *)tw_tab, k);
         __syncthreads();
@@ -322,6 +365,13 @@ __device__ inline void build_tables(cx<R> *ptab, cx<R> *scratch, const void *tw_
     __syncthreads();
 }
 
+// The twiddle source the passes take: the LDS tables, or the global table.
+template <class R, int LOGM>
+__device__ inline const cx<R> *pass_tables(const cx<R> *ptab, const void *tw_tab)
+{
+    return gtw_of<R>(LOGM) ? (const cx<R> *)tw_tab : ptab;
+}
+
 // Per distinct row length t (one work-group per job): the root table
 // exp(2 pi i m / t), m < t; for Bluestein lengths also the chirp
 // c_m = exp(i pi m^2 / t), m < t, and FFT_M of the circular chirp
@@ -332,7 +382,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void chirp_kernel(const ChirpJob *jobs
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
     __shared__ cx<R> buf[buf_elems(LOGM)];
-    __shared__ cx<R> ptab[ptab_elems(LOGM)];
+    __shared__ cx<R> ptab_lds[ptab_lds_elems<R>(LOGM)];
     const ChirpJob jb = jobs[blockIdx.x];
     const int t = jb.t, tid = threadIdx.x;
     cx<R> *roots = (cx<R> *)jb.roots;
@@ -343,7 +393,8 @@ __global__ __launch_bounds__(nt_of(LOGM)) void chirp_kernel(const ChirpJob *jobs
     }
     if (!jb.blue)
         return;
-    build_tables<R, LOGM>(ptab, buf, jb.tw_tab);
+    build_tables<R, LOGM>(ptab_lds, buf, jb.tw_tab);
+    const cx<R> *ptab = pass_tables<R, LOGM>(ptab_lds, jb.tw_tab);
     cx<R> *chirp = (cx<R> *)jb.chirp, *bh = (cx<R> *)jb.bhat;
     const bool act = tid < NTA;
     cx<R> v[PER];
@@ -534,10 +585,16 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
     __shared__ cx<R> buf[buf_elems(LOGM)];
-    __shared__ cx<R> ptab[ptab_elems(LOGM)];
+    __shared__ cx<R> ptab_lds[ptab_lds_elems<R>(LOGM)];
     const int tid = threadIdx.x;
     const bool act = tid < NTA;
-    build_tables<R, LOGM>(ptab, buf, a.hp[a.rows[0].prob].tw_tab);  // one set per launch (one M)
+    build_tables<R, LOGM>(ptab_lds, buf, a.hp[a.rows[0].prob].tw_tab);  // one set per launch (one M)
+    const cx<R> *ptab = pass_tables<R, LOGM>(ptab_lds, a.hp[a.rows[0].prob].tw_tab);
+
+    // the spectrum X of a row with two or more inverse-transform bands is kept
+    // in this work-group's slot of M elements (natural register pattern, each
+    // thread reading back only what it wrote), not in registers
+    cx<R> *xs = a.xs ? (cx<R> *)a.xs + (int64_t)blockIdx.x * M : nullptr;
 
     for (int ri = blockIdx.x; ri < a.nrows; ri += gridDim.x) {
         const RowRef rr = a.rows[ri];
@@ -546,66 +603,82 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
         auto x = gptr((const R *)hp.x + (int64_t)rr.row * hp.ld);
         const cx<R> *ch = (const cx<R> *)hp.chirp;
         const cx<R> *bh = (const cx<R> *)hp.bhat;
-        cx<R> v[PER], X[PER];
+        cx<R> v[PER];
         // loads are unconditional at clamped indices, then selected
         const int tid0 = act ? tid : 0;
 
-        // ---- X = DFT_t(x): natural order in buf (k < t) and in X (pattern)
+        // ---- X = DFT_t(x), natural order in buf (k < t)
         if (!hp.blue) {
 #pragma unroll
             for (int e = 0; e < PER; ++e)
                 v[e] = cx<R>{x[tid0 + e * NTA], (R)0};
             fft_lds<R, LOGM, false>(v, buf, ptab, act);
-#pragma unroll
-            for (int e = 0; e < PER; ++e)
-                X[e] = buf[pat_addr<LOGM>(tid0, e)];
         } else {
 #pragma unroll
             for (int e = 0; e < PER; ++e) {
                 const int n = tid0 + e * NTA, nc = min(n, t - 1);
-                const cx<R> a = cscale(cconj(gld(ch, nc)), x[nc]);
+                const cx<R> a = cscale(cconj(gld(fresh(ch), nc)), x[nc]);
                 v[e] = n < t ? a : cx<R>{0, 0};
             }
             fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
             for (int e = 0; e < PER; ++e)
-                v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
+                v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(fresh(bh), tid0 + e * NTA));
             fft_lds<R, LOGM, true>(v, buf, ptab, act);
             const R invm = (R)1 / (R)M;
 #pragma unroll
             for (int e = 0; e < PER; ++e) {
                 const int k = tid0 + e * NTA;
-                const cx<R> a = cscale(cmul(cconj(gld(ch, min(k, t - 1))), buf[pat_addr<LOGM>(tid0, e)]), invm);
-                X[e] = k < t ? a : cx<R>{0, 0};
+                const cx<R> a = cscale(cmul(cconj(gld(fresh(ch), min(k, t - 1))), buf[pat_addr<LOGM>(tid0, e)]), invm);
+                v[e] = k < t ? a : cx<R>{0, 0};
             }
             __syncthreads();  // buf fully read
             if (act) {
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
-                    buf[pat_addr<LOGM>(tid, e)] = X[e];
+                    buf[pat_addr<LOGM>(tid, e)] = v[e];
             }
             __syncthreads();
         }
 
         // ---- narrow bands: their bins to xbins, synthesised by band_synth_kernel
+        int ninv = 0;
         for (int b = 0; b < hp.nbands; ++b) {
             const BandBins bb = a.bins[hp.bin0 + b];
             if (bb.direct) {
                 cx<R> *dst = (cx<R> *)hp.xbins + ((int64_t)rr.row * hp.nbands + b) * DIRECT_KMAX;
                 for (int k = bb.klo + tid; k <= bb.khi; k += (int)blockDim.x)
                     gst(dst, k - bb.klo, buf[lpad(k)]);
+            } else {
+                ++ninv;
             }
         }
-        // ---- the other bands by inverse transform (each overwrites buf)
+        if (ninv >= 2 && act) {
+#pragma unroll
+            for (int e = 0; e < PER; ++e)
+                gst(fresh(xs), tid + e * NTA, buf[pat_addr<LOGM>(tid, e)]);
+        }
+        // ---- the other bands by inverse transform (each overwrites buf); the
+        // first takes X from buf, the later ones from the slot
+        int done = 0;
         for (int b = 0; b < hp.nbands; ++b) {
             const BandBins bb = a.bins[hp.bin0 + b];
             if (bb.direct)
                 continue;
             const GramDesc g = a.gd[hp.gram0 + b];
+            if (done++ == 0) {
+#pragma unroll
+                for (int e = 0; e < PER; ++e)
+                    v[e] = buf[pat_addr<LOGM>(tid0, e)];
+            } else {
+#pragma unroll
+                for (int e = 0; e < PER; ++e)
+                    v[e] = gld(fresh(xs), tid0 + e * NTA);
+            }
             if (!hp.blue) {
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
-                    v[e] = cscale(X[e], band_weight<R, FIR>(bb, tid0 + e * NTA, t));
+                    v[e] = cscale(v[e], band_weight<R, FIR>(bb, tid0 + e * NTA, t));
                 fft_lds<R, LOGM, true>(v, buf, ptab, act);
                 const R inv_t = (R)1 / (R)t;
                 store_band<R>(mode, g, hp, rr.row, [&](int n) { return cscale(buf[lpad(n)], inv_t); });
@@ -615,16 +688,16 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
                 for (int e = 0; e < PER; ++e) {
                     const int n = tid0 + e * NTA;
                     // X is 0 at n >= t, so the clamped chirp index changes nothing
-                    v[e] = cconj(cmul(cscale(X[e], band_weight<R, FIR>(bb, n, t)), gld(ch, min(n, t - 1))));
+                    v[e] = cconj(cmul(cscale(v[e], band_weight<R, FIR>(bb, n, t)), gld(fresh(ch), min(n, t - 1))));
                 }
                 fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
-                    v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
+                    v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(fresh(bh), tid0 + e * NTA));
                 fft_lds<R, LOGM, true>(v, buf, ptab, act);
                 const R zs = (R)1 / ((R)M * (R)t);
                 store_band<R>(mode, g, hp, rr.row,
-                              [&](int n) { return cscale(cmul(gld(ch, n), cconj(buf[lpad(n)])), zs); });
+                              [&](int n) { return cscale(cmul(gld(fresh(ch), n), cconj(buf[lpad(n)])), zs); });
             }
         }
     }
@@ -633,39 +706,36 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
 // -------------------------------------------------------------- adjoint --
 // dL/dx of one row: z_b = M_b x with M_b = IDFT diag(h_b) DFT Hermitian
 // (h_b real), so dL/dx = Re(sum_b M_b zbar_b) = Re(IDFT(sum_b h_b .*
-// DFT(zbar_b))), zbar_b being 0 outside the window.  The spectrum sum S stays
-// in registers (natural pattern); with a single band (ONE) it is the band's
-// own spectrum and needs no second register array.
-template <class R, int LOGM, bool ONE, bool FIR>
+// DFT(zbar_b))), zbar_b being 0 outside the window.  With several bands the
+// running spectrum sum is kept in the work-group's slot of M elements (each
+// thread reading back only what it wrote), not in registers.
+template <class R, int LOGM, bool FIR>
 __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArgs a)
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
     __shared__ cx<R> buf[buf_elems(LOGM)];
-    __shared__ cx<R> ptab[ptab_elems(LOGM)];
+    __shared__ cx<R> ptab_lds[ptab_lds_elems<R>(LOGM)];
     const int tid = threadIdx.x;
     const bool act = tid < NTA;
-    build_tables<R, LOGM>(ptab, buf, a.hp[a.rows[0].prob].tw_tab);
+    build_tables<R, LOGM>(ptab_lds, buf, a.hp[a.rows[0].prob].tw_tab);
+    const cx<R> *ptab = pass_tables<R, LOGM>(ptab_lds, a.hp[a.rows[0].prob].tw_tab);
+    cx<R> *xs = a.xs ? (cx<R> *)a.xs + (int64_t)blockIdx.x * M : nullptr;
 
     for (int ri = blockIdx.x; ri < a.nrows; ri += gridDim.x) {
         const RowRef rr = a.rows[ri];
         const HilbertProb hp = a.hp[rr.prob];
-        const int t = hp.t;
+        const int t = hp.t, nb = hp.nbands;
         const cx<R> *ch = (const cx<R> *)hp.chirp;
         const cx<R> *bh = (const cx<R> *)hp.bhat;
         const int tid0 = act ? tid : 0;
-        cx<R> v[PER], S[ONE ? 1 : PER];
-        if constexpr (!ONE) {
-#pragma unroll
-            for (int e = 0; e < PER; ++e)
-                S[e] = cx<R>{0, 0};
-        }
-        for (int b = 0; b < (ONE ? 1 : hp.nbands); ++b) {
+        cx<R> v[PER];
+        for (int b = 0; b < nb; ++b) {
             const BandBins bb = a.bins[hp.bin0 + b];
             const GramDesc g = a.gd[hp.gram0 + b];
             const cx<R> *zb = (const cx<R> *)g.zbuf + (int64_t)rr.row * g.ldz;
             auto v_at = [&](int n) -> cx<R> {  // zbar on the full row, 0 off the window
                 const int s = n - hp.t0;
-                const cx<R> z = gld(zb, min(max(s, 0), hp.tw - 1));
+                const cx<R> z = gld(fresh(zb), min(max(s, 0), hp.tw - 1));
                 return (s >= 0 && s < hp.tw) ? z : cx<R>{0, 0};
             };
             // v <- h_b .* DFT_t(zbar_b)
@@ -681,31 +751,37 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
 #pragma unroll
                 for (int e = 0; e < PER; ++e) {
                     const int n = tid0 + e * NTA;
-                    v[e] = cmul(v_at(n), cconj(gld(ch, min(n, t - 1))));  // v_at is 0 at n >= t
+                    v[e] = cmul(v_at(n), cconj(gld(fresh(ch), min(n, t - 1))));  // v_at is 0 at n >= t
                 }
                 fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
                 for (int e = 0; e < PER; ++e)
-                    v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
+                    v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(fresh(bh), tid0 + e * NTA));
                 fft_lds<R, LOGM, true>(v, buf, ptab, act);
                 const R invm = (R)1 / (R)M;
 #pragma unroll
                 for (int e = 0; e < PER; ++e) {
                     const int k = tid0 + e * NTA;
-                    const cx<R> d = cmul(cconj(gld(ch, min(k, t - 1))), buf[pat_addr<LOGM>(tid0, e)]);
+                    const cx<R> d = cmul(cconj(gld(fresh(ch), min(k, t - 1))), buf[pat_addr<LOGM>(tid0, e)]);
                     v[e] = cscale(d, k < t ? band_weight<R, FIR>(bb, k, t) * invm : (R)0);
                 }
             }
-            if constexpr (!ONE) {
+            // the band sum: bands 0 .. nb - 2 into the slot, the last one added to it in v
+            if (nb > 1 && act) {
+                if (b == 0) {
 #pragma unroll
-                for (int e = 0; e < PER; ++e)
-                    S[e] = cadd(S[e], v[e]);
+                    for (int e = 0; e < PER; ++e)
+                        gst(fresh(xs), tid + e * NTA, v[e]);
+                } else if (b < nb - 1) {
+#pragma unroll
+                    for (int e = 0; e < PER; ++e)
+                        gst(fresh(xs), tid + e * NTA, cadd(gld(fresh(xs), tid + e * NTA), v[e]));
+                } else {
+#pragma unroll
+                    for (int e = 0; e < PER; ++e)
+                        v[e] = cadd(gld(fresh(xs), tid + e * NTA), v[e]);
+                }
             }
-        }
-        if constexpr (!ONE) {
-#pragma unroll
-            for (int e = 0; e < PER; ++e)
-                v[e] = S[e];
         }
         // x_bar = Re(IDFT_t(S)), S in v
         auto xb = gptr((R *)hp.xbar + (int64_t)rr.row * hp.ld);
@@ -719,28 +795,33 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
 #pragma unroll
             for (int e = 0; e < PER; ++e) {
                 const int n = tid0 + e * NTA;
-                v[e] = cconj(cmul(v[e], gld(ch, min(n, t - 1))));  // S is 0 at n >= t
+                v[e] = cconj(cmul(v[e], gld(fresh(ch), min(n, t - 1))));  // S is 0 at n >= t
             }
             fft_lds<R, LOGM, false>(v, buf, ptab, act);
 #pragma unroll
             for (int e = 0; e < PER; ++e)
-                v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(bh, tid0 + e * NTA));
+                v[e] = cmul(buf[pat_addr<LOGM>(tid0, e)], gld(fresh(bh), tid0 + e * NTA));
             fft_lds<R, LOGM, true>(v, buf, ptab, act);
             const R scale = (R)1 / ((R)M * (R)t);
             for (int n = tid; n < t; n += blockDim.x)
-                xb[n] = cmul(cconj(gld(ch, n)), buf[lpad(n)]).x * scale;
+                xb[n] = cmul(cconj(gld(fresh(ch), n)), buf[lpad(n)]).x * scale;
         }
     }
 }
 
 // ------------------------------------------------------------ dispatch --
+// Work-groups of a grid-stride transform launch: every one resident at once,
+// and no more than the spectrum slots the host reserved (when it did).
 template <class K>
-int grid_for(K kernel, int nt, int rows, int cus)
+int grid_for(K kernel, int nt, int rows, int cus, const HilbertArgs *ha)
 {
     int occ = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, nt, 0) != hipSuccess || occ < 1)
         occ = 1;
-    return std::max(1, std::min(rows, cus * occ));
+    int n = std::min(rows, cus * occ);
+    if (ha->xs)
+        n = std::min(n, ha->xslots);
+    return std::max(1, n);
 }
 
 template <class R, int LOGM>
@@ -752,25 +833,19 @@ hipError_t launch_sized(int kind, int mode, const HilbertArgs *ha, const ChirpJo
         chirp_kernel<R, LOGM><<<n, NT, 0, s>>>(jobs);
     } else if (kind == 1) {
         if (ha->fir) {
-            const int nwg = grid_for(hilbert_kernel<R, LOGM, true>, NT, ha->nrows, cus);
+            const int nwg = grid_for(hilbert_kernel<R, LOGM, true>, NT, ha->nrows, cus, ha);
             hilbert_kernel<R, LOGM, true><<<nwg, NT, 0, s>>>(*ha, mode);
         } else {
-            const int nwg = grid_for(hilbert_kernel<R, LOGM, false>, NT, ha->nrows, cus);
+            const int nwg = grid_for(hilbert_kernel<R, LOGM, false>, NT, ha->nrows, cus, ha);
             hilbert_kernel<R, LOGM, false><<<nwg, NT, 0, s>>>(*ha, mode);
         }
     } else {
-        if (ha->nbands == 1 && !ha->fir) {
-            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true, false>, NT, ha->nrows, cus);
-            hilbert_adjoint_kernel<R, LOGM, true, false><<<nwg, NT, 0, s>>>(*ha);
-        } else if (ha->nbands == 1) {
-            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true, true>, NT, ha->nrows, cus);
-            hilbert_adjoint_kernel<R, LOGM, true, true><<<nwg, NT, 0, s>>>(*ha);
-        } else if (!ha->fir) {
-            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false, false>, NT, ha->nrows, cus);
-            hilbert_adjoint_kernel<R, LOGM, false, false><<<nwg, NT, 0, s>>>(*ha);
+        if (ha->fir) {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true>, NT, ha->nrows, cus, ha);
+            hilbert_adjoint_kernel<R, LOGM, true><<<nwg, NT, 0, s>>>(*ha);
         } else {
-            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false, true>, NT, ha->nrows, cus);
-            hilbert_adjoint_kernel<R, LOGM, false, true><<<nwg, NT, 0, s>>>(*ha);
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false>, NT, ha->nrows, cus, ha);
+            hilbert_adjoint_kernel<R, LOGM, false><<<nwg, NT, 0, s>>>(*ha);
         }
     }
     return hipGetLastError();
@@ -870,6 +945,13 @@ hipError_t launch_band_synth(int mode, const HilbertArgs &a, int njobs, hipStrea
     else
         band_synth_kernel<float><<<njobs, 256, 0, s>>>(a, mode);
     return hipGetLastError();
+}
+
+int fft_wg_per_cu(bool f64, int logm)
+{
+    const size_t lds = f64 ? (size_t)(buf_elems(logm) + ptab_lds_elems<double>(logm)) * 16
+                           : (size_t)(buf_elems(logm) + ptab_lds_elems<float>(logm)) * 8;
+    return (int)std::max<size_t>(1, std::min<size_t>(16, (size_t)160 * 1024 / lds));
 }
 
 hipError_t launch_hilbert(int mode, const HilbertArgs &a, int cus, hipStream_t s)

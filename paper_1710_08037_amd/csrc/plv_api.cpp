@@ -625,6 +625,8 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             ha.gd = (const GramDesc *)(ws + plan.desc_off);
             ha.nbands = nbands;
             ha.fir = plan.nfirjobs > 0 ? 1 : 0;
+            ha.xs = plan.xs_slots[c] ? ws + plan.xs_off : nullptr;
+            ha.xslots = plan.xs_slots[c];
             if ((e = launch_hilbert(mode, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal kernel launch");
             tm.launched();
@@ -1173,6 +1175,8 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
             ha.rows = (const RowRef *)(ws + plan.row_off) + class_start[c];
             ha.nrows = class_count[c];
             ha.logm = plan.tw_logm[c];
+            ha.xs = plan.xs_slots[c] ? ws + plan.xs_off : nullptr;
+            ha.xslots = plan.xs_slots[c];
             if ((e = launch_hilbert(mode, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal kernel launch");
             ++nl;
@@ -1276,6 +1280,8 @@ static plv_status enqueue_backward(plv_ctx *ctx, const Plan &plan, const plv_pro
             ha.rows = (const RowRef *)(ws + plan.row_off) + class_start[c];
             ha.nrows = class_count[c];
             ha.logm = plan.tw_logm[c];
+            ha.xs = plan.xs_slots[c] ? ws + plan.xs_off : nullptr;
+            ha.xslots = plan.xs_slots[c];
             if ((e = launch_hilbert_adjoint(f64, ha, ctx->cus, s)) != hipSuccess)
                 return hip_fail(ctx, e, "analytic-signal adjoint kernel launch");
             tm.launched();

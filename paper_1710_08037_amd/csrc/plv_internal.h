@@ -231,8 +231,10 @@ struct HilbertArgs {
     int32_t nprob;        // band synthesis: problems, and the running work-group counts
     const int32_t *synth_prefix;  //   [nprob + 1] of the problems (see band_synth_kernel)
     int32_t fir;          // some band of the call is an FIR band (selects the kernel variant)
-    int32_t pad2_;
+    int32_t xslots;       // work-group slots at xs (the transform launches use at most this many)
     const int32_t *dft_prefix;    // DFT-bins kernel: [nprob + 1] running work-group counts
+    void *xs;             // calls with several bands: [xslots][M] complex, a row's spectrum per
+                          // work-group (forward) or its band sum (adjoint); nullptr otherwise
 };
 
 // Set-up for one distinct row length t: its root table, and for a Bluestein
@@ -319,7 +321,7 @@ hipError_t launch_diag(int mode, const GramDesc &g, hipStream_t s);
 int herk_occupancy(int mode, int bm);
 // FFT stage (fft.hip).  f64 selects double precision tables and transforms.
 constexpr int FFT_MAXLOG_F32 = 13;  // M <= 8192 complex FP32 transforms in LDS
-constexpr int FFT_MAXLOG_F64 = 12;  // M <= 4096 complex FP64
+constexpr int FFT_MAXLOG_F64 = 13;  // M <= 8192 complex FP64 (pass twiddles from global memory at 8192)
 hipError_t launch_twiddles(bool f64, void *tab, int logm, hipStream_t s);
 // jobs: device array of njobs set-ups that all have this logm
 hipError_t launch_chirps(bool f64, int logm, const ChirpJob *jobs, int njobs, hipStream_t s);
@@ -329,6 +331,9 @@ hipError_t launch_fir_weights(bool f64, const FirJob *jobs, int njobs, int max_t
 // kernel's occupancy
 hipError_t launch_hilbert(int mode, const HilbertArgs &a, int cus, hipStream_t s);
 hipError_t launch_hilbert_adjoint(bool f64, const HilbertArgs &a, int cus, hipStream_t s);
+// Upper bound on the resident work-groups per CU of a transform kernel of
+// size 2^logm (from its LDS), at most 16: the spectrum slots reserved per CU.
+int fft_wg_per_cu(bool f64, int logm);
 // after launch_hilbert: the bands with BandBins::direct of every problem, from
 // their bins in HilbertProb::xbins; njobs = a.synth_prefix[a.nprob] work-groups
 hipError_t launch_band_synth(int mode, const HilbertArgs &a, int njobs, hipStream_t s);

@@ -448,6 +448,20 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
             if (!fir_bands.empty())
                 plan.fir_max_t = std::max(plan.fir_max_t, l.t);
         }
+        // several bands: one spectrum slot of M elements per resident
+        // work-group of the transform launches (one region, reused by each
+        // FFT size in turn)
+        plan.xs_slots.assign(plan.tw_logm.size(), 0);
+        if (nbands >= 2) {
+            size_t most = 0;
+            for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+                const int lg = plan.tw_logm[c];
+                plan.xs_slots[c] = std::max(1, cus) * fft_wg_per_cu(mode == M_F64, lg);
+                most = std::max(most, (size_t)plan.xs_slots[c] * ((size_t)1 << lg) * csz);
+            }
+            plan.xs_off = off;
+            off += align256(most);
+        }
         // band-pass bands may be synthesised from their bins: a slot of
         // DIRECT_KMAX bins per row and band (fs, and so the bin counts, are
         // only known at the call)

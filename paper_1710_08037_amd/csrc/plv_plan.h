@@ -79,6 +79,8 @@ struct Plan {
     size_t hp_off = 0, bin_off = 0, row_off = 0, job_off = 0;
     size_t synth_off = 0;  // band synthesis: running work-group counts [nprob + 1]
     size_t dftp_off = 0;   // DFT-bins kernel: running work-group counts [nprob + 1]
+    size_t xs_off = 0;     // calls with several bands: spectrum slots of the transform launches
+    std::vector<int> xs_slots;  // per FFT size (as tw_logm): slots there (0: none reserved)
     std::vector<size_t> fir_r_off;  // per band: the FIR taps' autocorrelation (FP64, in the tables)
     size_t firjob_off = 0;          // FirJob per (row length, FIR band), in the tables
     int nfirjobs = 0, fir_max_t = 0;

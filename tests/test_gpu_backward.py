@@ -100,10 +100,13 @@ def test_backward_real_against_oracle(prec, t):
 
 
 @pytest.mark.parametrize("prec", ["f64", "split_bf16"])
-def test_backward_real_bands_window(prec):
-    n, t, fs = 8, 600, 1000.0
+@pytest.mark.parametrize("t", [600, 3001, 8192])
+def test_backward_real_bands_window(prec, t):
+    """Two bands (their band sum kept in the work-group's spectrum slot),
+    Bluestein lengths of M = 2048 and 8192 and a plain 8192-point one."""
+    n, fs = 8, 1000.0
     bands = [(8.0, 12.0), (18.0, 22.0)]
-    win = (50, 560)
+    win = (50, t - 40)
     x = synth.glag_real(n, t, fs, 4, (8, 22), seed=81)
     xd = dev(x, prec, True)
     out = plv_mod().from_real(xd, fs, bands=bands, prec=prec, window=win, want_g=True)
@@ -171,6 +174,45 @@ def test_f64_directional_finite_differences():
         fd = (loss(x + eps * d) - loss(x - eps * d)) / (2 * eps)
         an = float((g * d).sum())
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3), (k, fd, an)
+
+
+def test_f64_directional_finite_differences_full_size():
+    """The differentiable case at its own size, N = 2048 real signals of
+    T = 8192 samples, in FP64 (8192-point transforms): the adjoint's
+    directional derivative of L = sum_{i<j} (ciPLV_ij - C*_ij)^2 against
+    central differences of the GPU FP64 forward in 16 random directions.
+
+    A unit direction in N T = 1.7e7 coordinates sees only about |g| / 4096 of
+    the gradient (about 2e-3 here), so the differences take a large step,
+    h = 1e-3 max|x|, with Richardson's extrapolation from h and 2h (error
+    O(h^4)); what is left is the rounding of L itself, about 12 ulp of L per
+    evaluation as measured, bounded here by 32 ulp over the step."""
+    n, t, fs = 2048, 8192, 1000.0
+    x = dev(synth.glag_real(n, t, fs, 32, (8, 12), seed=synth.seed_for(5)), "f64", True)
+    cstar = torch.from_numpy(synth.sparse_target(n, seed=synth.seed_for(5, 1))).cuda()
+    upper = torch.triu(torch.ones(n, n, dtype=torch.float64, device="cuda"), 1)
+
+    def loss(xx):
+        c = plv_mod().from_real(xx, fs, prec="f64", want=("ciplv",))["ciplv"][0]
+        return float((((c - cstar) ** 2) * upper).sum())
+
+    print("f64 finite differences: N=2048 T=8192, 16 directions", flush=True)
+    out = plv_mod().from_real(x, fs, prec="f64", want_g=True)
+    dc = (2 * (out["ciplv"][0] - cstar) * upper)[None]
+    g = plv_mod().backward_batch([x], [out["g"]], [(None, None, dc)], fs=fs, prec="f64")[0]
+    lval = loss(x)
+    h = 1e-3 * float(x.abs().max())
+    noise = 32 * 2.0 ** -53 * lval / h
+    rng = np.random.default_rng(15)
+    for k in range(16):
+        d = torch.from_numpy(rng.standard_normal((n, t))).cuda()
+        d /= d.norm()
+        f1 = (loss(x + h * d) - loss(x - h * d)) / (2 * h)
+        f2 = (loss(x + 2 * h * d) - loss(x - 2 * h * d)) / (4 * h)
+        fd = (4 * f1 - f2) / 3
+        an = float((g * d).sum())
+        print("direction %d: fd %.12e analytic %.12e" % (k, fd, an), flush=True)
+        assert abs(fd - an) <= 2e-6 * abs(an) + noise, (k, fd, an, noise)
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "f32"])

@@ -31,10 +31,10 @@ def exact_real(x, prec):
 
 
 def fits_lds_fft(t, prec):
-    """The FFT stage keeps a row's transforms in LDS: M <= 8192 (FP32 modes) or
-    4096 (FP64), M = t for a power of two, else the power of two >= 2t - 1."""
+    """The FFT stage keeps a row's transforms in LDS: M <= 8192 in every mode,
+    M = t for a power of two, else the power of two >= 2t - 1."""
     m = t if (t >= 2 and t & (t - 1) == 0) else 1 << max(1, (2 * t - 2).bit_length())
-    return m <= (4096 if prec == "f64" else 8192)
+    return m <= 8192
 
 
 def to_np(out, b):
@@ -53,7 +53,7 @@ def test_small_lagged_oscillators_plain_analytic_signal(prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16"])
-@pytest.mark.parametrize("t", [1, 2, 3, 97, 500, 777, 1000, 997, 4000])
+@pytest.mark.parametrize("t", [1, 2, 3, 97, 500, 777, 1000, 997, 4000, 4096, 8192, 4097])
 def test_bluestein_and_radix2_lengths(prec, t):
     n = 19
     x = synth.glag_real(n, t, 1000.0, 3, (8, 12), seed=300 + t)
@@ -98,8 +98,6 @@ def test_grouped_uneven_problems_with_bands(prec):
     fs = 1000.0
     bands = synth.bands_hz()
     shapes = [(68, 700), (148, 1024), (5, 999), (40, 2500), (68, 4000)]
-    if prec == "f64":   # FP64 rows must fit a 4096-point transform
-        shapes = [(68, 700), (148, 1024), (5, 999), (40, 2048), (30, 1500)]
     xs = [synth.glag_real(n, t, fs, 4, (2, 42), seed=500 + k) for k, (n, t) in enumerate(shapes)]
     outs = plv_mod().from_real_batch([real_dev(x, prec) for x in xs], fs, bands=bands, prec=prec, want_g=True)
     torch.cuda.synchronize()
