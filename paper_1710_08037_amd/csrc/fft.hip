@@ -489,6 +489,7 @@ __device__ inline void store_band(int mode, const GramDesc &g, const HilbertProb
 // Work-groups of problem q: nbands x ceil(L / SYNTH_S) x ceil(n / SYNTH_R), L the
 // samples written per row (tpad for phasor planes, the window for the backward's
 // complex z); the host stores the running sums in a table of nprob + 1 entries.
+// FP64 mode; the FP32 modes take the matrix-product form below.
 template <class R>
 __global__ __launch_bounds__(256) void band_synth_kernel(HilbertArgs a, int mode)
 {
@@ -574,6 +575,168 @@ __global__ __launch_bounds__(256) void band_synth_kernel(HilbertArgs a, int mode
             }
             store4_mode<R>(mode, plane_at((uint8_t *)g.u, g.cstride, g.chunk, g.npad, cbytes_of(mode), row, s0),
                            g.plane_bytes, ur, ui);
+        }
+    }
+}
+
+// FP32 modes: the same sums as a matrix product on MFMA.  With nb = t0 +
+// sb SYNTH_S the full-row index of the block's first sample and n = nb + j:
+//   z(n) = sum_{m<K} R[j][m] Y[m],   R[j][m] = exp(2 pi i (klo+m) j / t),
+//   Y[m] = (2/t) exp(2 pi i (klo+m) nb / t) X_{klo+m}.
+// R is one table for every row of the work-group (SYNTH_S x K, from the root
+// table, in LDS); each row's Y is its B operand, formed as the row's bins
+// times the block's rotations.  v_mfma_f32_16x16x4f32 with the samples as
+// the row index and the signal rows as the column index: a wave takes 16
+// rows at a time, and afterwards lane l holds samples 4 (l / 16) .. + 3 of
+// every 16-sample column block for row l % 16, the store pattern of the
+// Horner kernel (16 rows x 64 bytes of one plane stage per wave and store).
+// Complex: Re z = Rr.Yr - Ri.Yi, Im z = Rr.Yi + Ri.Yr, four real products.
+template <int MODE>
+__global__ __launch_bounds__(256, 4) void band_synth_mfma_kernel(HilbertArgs a)
+{
+    static_assert(SYNTH_S == 64 && SYNTH_R % 64 == 0, "4 column blocks of 16 samples; 4 waves of 16 rows");
+    constexpr int RS = SYNTH_S + 16;  // R row stride: the 4 K-rows one MFMA step reads land in distinct banks
+    constexpr int KS = DIRECT_KMAX / 4;  // MFMA steps of 4 bins, at most
+    __shared__ float rre[DIRECT_KMAX * RS], rim[DIRECT_KMAX * RS];
+    __shared__ cx<float> pk[DIRECT_KMAX];
+    const int job = blockIdx.x;
+    int lo = 0, hi = a.nprob;  // prefix[lo] <= job < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a.synth_prefix[mid] <= job)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int q = lo;
+    const HilbertProb hp = a.hp[q];
+    const GramDesc g0 = a.gd[hp.gram0];
+    const int len0 = g0.zbuf ? hp.tw : g0.tpad;  // samples synthesised per row (host counts the same)
+    const int nsb = (len0 + SYNTH_S - 1) / SYNTH_S;
+    int rest = job - a.synth_prefix[q];
+    const int b = rest % hp.nbands;
+    rest /= hp.nbands;
+    const int sb = rest % nsb, rc = rest / nsb;
+    const BandBins bb = a.bins[hp.bin0 + b];
+    if (!bb.direct)
+        return;
+    const GramDesc g = a.gd[hp.gram0 + b];
+    const int t = hp.t, klo = bb.klo, khi = bb.khi;
+    const int nk = khi >= klo ? khi - klo + 1 : 0;  // <= DIRECT_KMAX (host rule)
+    const int kl = nk ? klo : 0, kp = (nk + 3) & ~3;
+    const int limit = g.zbuf ? hp.tw : g.tpad;
+    const int tid = threadIdx.x;
+    const cx<float> *roots = (const cx<float> *)hp.roots;
+    const int nb = hp.t0 + sb * SYNTH_S;  // < t + SYNTH_S; (kl + m) nb < 2^31 for t <= 8192
+
+    const int lane = tid & 63, wv = tid >> 6, lr = lane & 15, lk = lane >> 4;
+    const cx<float> *xsrc = (const cx<float> *)hp.xbins + (int64_t)b * DIRECT_KMAX;
+    const int64_t xrow = (int64_t)hp.nbands * DIRECT_KMAX;  // bins of one row to the next
+    const int r_end = min(hp.n, (rc + 1) * SYNTH_R);
+    const int rfirst = rc * SYNTH_R + wv * 16;
+    // The bins of a 16-row group, raw (m < kp <= DIRECT_KMAX stays inside
+    // each row's slot; bins past nk and rows past the end are selected away
+    // where used).  Each group's loads are issued one group ahead.
+    auto load_bins = [&](int r0, cx<float> (&y)[KS]) {
+        const cx<float> *xr = xsrc + (int64_t)min(r0 + lr, r_end - 1) * xrow + lk;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            if (s * 4 < kp)
+                y[s] = gld(xr, s * 4);
+    };
+    cx<float> ya[KS], yb[KS];
+    if (rfirst < r_end)
+        load_bins(rfirst, ya);
+
+    // ---- R (zero rows up to kp): four threads per bin, 16 consecutive j
+    // each, the root index stepped by kl + m (< t) from one remainder
+    for (int e = tid; e < kp * 4; e += 256) {
+        const int m = e >> 2, j0 = (e & 3) * 16, step = kl + m;
+        int idx = m < nk ? (step * j0) % t : 0;
+#pragma unroll
+        for (int j = j0; j < j0 + 16; ++j) {
+            const cx<float> r = m < nk ? gld(roots, idx) : cx<float>{0.0f, 0.0f};
+            rre[m * RS + j] = r.x;
+            rim[m * RS + j] = r.y;
+            idx += step;
+            idx = idx >= t ? idx - t : idx;
+        }
+    }
+    if (tid < kp)
+        pk[tid] = tid < nk ? cscale(gld(roots, ((kl + tid) * nb) % t), 2.0f / (float)t) : cx<float>{0.0f, 0.0f};
+    __syncthreads();
+
+    for (int r0 = rfirst; r0 < r_end; r0 += 64) {  // wave-uniform bounds
+        const int row = r0 + lr;
+        const bool rok = row < r_end;
+        if (r0 + 64 < r_end)
+            load_bins(r0 + 64, yb);
+        vf4 zr[4], zi[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            zr[c] = vf4{0.0f, 0.0f, 0.0f, 0.0f};
+            zi[c] = vf4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            if (s * 4 >= kp)
+                break;
+            const int m = s * 4 + lk;
+            const cx<float> x = (rok && m < nk) ? ya[s] : cx<float>{0.0f, 0.0f};
+            const cx<float> yv = cmul(x, pk[m]);
+            const float *ar = rre + m * RS + lr, *ai = rim + m * RS + lr;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float rr_ = ar[c * 16], ri_ = ai[c * 16];
+                zr[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(rr_, yv.x, zr[c], 0, 0, 0);
+                zr[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ri_, -yv.y, zr[c], 0, 0, 0);
+                zi[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(rr_, yv.y, zi[c], 0, 0, 0);
+                zi[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ri_, yv.x, zi[c], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            ya[s] = yb[s];
+        if (!rok)
+            continue;
+        if (g.zbuf) {
+            cx<float> *zrow = (cx<float> *)g.zbuf + (int64_t)row * g.ldz;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int s0 = sb * SYNTH_S + c * 16 + lk * 4;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (s0 + v < hp.tw)
+                        gst(zrow, s0 + v, cx<float>{zr[c][v], zi[c][v]});
+            }
+            continue;
+        }
+        // plane address: a 16-sample column block lies in one K-chunk (chunks
+        // are whole granules) and in one or two plane stages; its uniform part
+        // per block, the lane's part (row, its 4 samples) once per row group
+        constexpr int CB = cbytes_of(MODE), LSPS = CB == 4 ? 4 : 3;  // log2 samples per stage
+        const int64_t lane_off = ((int64_t)((lk * 4) >> LSPS) * g.npad + row) * 64 + ((lk * 4) & ((1 << LSPS) - 1)) * CB;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int sbk = sb * SYNTH_S + c * 16;  // wave-uniform
+            if (sbk >= limit)
+                continue;
+            const int ch = sbk < g.chunk ? 0 : sbk / g.chunk, k = sbk - ch * g.chunk;
+            uint8_t *dst = (uint8_t *)g.u + ch * g.cstride + ((int64_t)(k >> LSPS) * g.npad) * 64 + lane_off;
+            const float re[4] = {zr[c][0], zr[c][1], zr[c][2], zr[c][3]};
+            const float im[4] = {zi[c][0], zi[c][1], zi[c][2], zi[c][3]};
+            float ur[4], ui[4];
+            unit_phasor4(re, im, ur, ui);
+            if (sbk + 16 > hp.tw) {  // zero phasors past the window
+                const int s0 = sbk + lk * 4;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const bool in = s0 + v < hp.tw;
+                    ur[v] = in ? ur[v] : 0.0f;
+                    ui[v] = in ? ui[v] : 0.0f;
+                }
+            }
+            store4<MODE>(dst, g.plane_bytes, ur, ui);
         }
     }
 }
@@ -940,10 +1103,13 @@ hipError_t launch_band_synth(int mode, const HilbertArgs &a, int njobs, hipStrea
         return hipSuccess;
     if (mode < M_F64 || mode > M_F16 || a.nprob <= 0 || !a.synth_prefix)
         return hipErrorInvalidValue;
-    if (mode == M_F64)
-        band_synth_kernel<double><<<njobs, 256, 0, s>>>(a, mode);
-    else
-        band_synth_kernel<float><<<njobs, 256, 0, s>>>(a, mode);
+    switch (mode) {
+    case M_F64: band_synth_kernel<double><<<njobs, 256, 0, s>>>(a, mode); break;
+    case M_F32: band_synth_mfma_kernel<M_F32><<<njobs, 256, 0, s>>>(a); break;
+    case M_SPLIT: band_synth_mfma_kernel<M_SPLIT><<<njobs, 256, 0, s>>>(a); break;
+    case M_BF16: band_synth_mfma_kernel<M_BF16><<<njobs, 256, 0, s>>>(a); break;
+    default: band_synth_mfma_kernel<M_F16><<<njobs, 256, 0, s>>>(a); break;
+    }
     return hipGetLastError();
 }
 

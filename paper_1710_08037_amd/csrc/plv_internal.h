@@ -341,7 +341,7 @@ constexpr int SYNTH_S = 64, SYNTH_R = 256;  // samples and rows per band-synthes
 // Problems whose bands are all narrow, with at most DFT_MAX_BINS bins in all,
 // take their bins from the DFT-bins kernel (dft.hip, FP32 modes) instead of
 // the transform kernel; njobs = a.dft_prefix[a.nprob] work-groups of 64 rows.
-constexpr int DFT_MAX_BINS = 128;
+constexpr int DFT_MAX_BINS = 96;
 constexpr int DFT_ROWS_PER_WG = 64;
 hipError_t launch_dft_bins(const HilbertArgs &a, int njobs, hipStream_t s);
 hipError_t launch_planes_t(int mode, const BwdPlanesArgs &a, hipStream_t s);
