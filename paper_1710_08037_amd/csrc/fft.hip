@@ -623,7 +623,7 @@ __global__ __launch_bounds__(256, 4) void band_synth_mfma_kernel(HilbertArgs a)
     const GramDesc g = a.gd[hp.gram0 + b];
     const int t = hp.t, klo = bb.klo, khi = bb.khi;
     const int nk = khi >= klo ? khi - klo + 1 : 0;  // <= DIRECT_KMAX (host rule)
-    const int kl = nk ? klo : 0, kp = (nk + 3) & ~3;
+    const int kl = nk ? klo : 0, kp = max(4, (nk + 3) & ~3);  // an empty band: one step of zeros
     const int limit = g.zbuf ? hp.tw : g.tpad;
     const int tid = threadIdx.x;
     const cx<float> *roots = (const cx<float> *)hp.roots;
@@ -666,11 +666,26 @@ __global__ __launch_bounds__(256, 4) void band_synth_mfma_kernel(HilbertArgs a)
         pk[tid] = tid < nk ? cscale(gld(roots, ((kl + tid) * nb) % t), 2.0f / (float)t) : cx<float>{0.0f, 0.0f};
     __syncthreads();
 
-    for (int r0 = rfirst; r0 < r_end; r0 += 64) {  // wave-uniform bounds
+    // the column blocks' plane offsets: a 16-sample block lies in one K-chunk
+    // (chunks are whole granules) and its 4-sample runs in one plane stage;
+    // the uniform part per block here, the lane's part (row, its 4 samples)
+    // per row group
+    constexpr int CB = cbytes_of(MODE), LSPS = CB == 4 ? 4 : 3;  // log2 samples per stage
+    int64_t boff[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int sbk = sb * SYNTH_S + c * 16;
+        const int ch = sbk < g.chunk ? 0 : sbk / g.chunk, k = sbk - ch * g.chunk;
+        boff[c] = ch * g.cstride + ((int64_t)(k >> LSPS) * g.npad) * 64;
+    }
+
+    // one 16-row group: its product from y (the group's bins), the next
+    // group's bins into yn, then the normalisation and store
+    auto group = [&](int r0, const cx<float> (&y)[KS], cx<float> (&yn)[KS]) {
         const int row = r0 + lr;
         const bool rok = row < r_end;
         if (r0 + 64 < r_end)
-            load_bins(r0 + 64, yb);
+            load_bins(r0 + 64, yn);
         vf4 zr[4], zi[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -679,10 +694,10 @@ __global__ __launch_bounds__(256, 4) void band_synth_mfma_kernel(HilbertArgs a)
         }
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-            if (s * 4 >= kp)
+            if (s > 0 && s * 4 >= kp)  // kp >= 4: the first step always runs
                 break;
             const int m = s * 4 + lk;
-            const cx<float> x = (rok && m < nk) ? ya[s] : cx<float>{0.0f, 0.0f};
+            const cx<float> x = (rok && m < nk) ? y[s] : cx<float>{0.0f, 0.0f};
             const cx<float> yv = cmul(x, pk[m]);
             const float *ar = rre + m * RS + lr, *ai = rim + m * RS + lr;
 #pragma unroll
@@ -694,11 +709,8 @@ __global__ __launch_bounds__(256, 4) void band_synth_mfma_kernel(HilbertArgs a)
                 zi[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ri_, yv.x, zi[c], 0, 0, 0);
             }
         }
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-            ya[s] = yb[s];
         if (!rok)
-            continue;
+            return;
         if (g.zbuf) {
             cx<float> *zrow = (cx<float> *)g.zbuf + (int64_t)row * g.ldz;
 #pragma unroll
@@ -709,20 +721,14 @@ __global__ __launch_bounds__(256, 4) void band_synth_mfma_kernel(HilbertArgs a)
                     if (s0 + v < hp.tw)
                         gst(zrow, s0 + v, cx<float>{zr[c][v], zi[c][v]});
             }
-            continue;
+            return;
         }
-        // plane address: a 16-sample column block lies in one K-chunk (chunks
-        // are whole granules) and in one or two plane stages; its uniform part
-        // per block, the lane's part (row, its 4 samples) once per row group
-        constexpr int CB = cbytes_of(MODE), LSPS = CB == 4 ? 4 : 3;  // log2 samples per stage
         const int64_t lane_off = ((int64_t)((lk * 4) >> LSPS) * g.npad + row) * 64 + ((lk * 4) & ((1 << LSPS) - 1)) * CB;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int sbk = sb * SYNTH_S + c * 16;  // wave-uniform
             if (sbk >= limit)
                 continue;
-            const int ch = sbk < g.chunk ? 0 : sbk / g.chunk, k = sbk - ch * g.chunk;
-            uint8_t *dst = (uint8_t *)g.u + ch * g.cstride + ((int64_t)(k >> LSPS) * g.npad) * 64 + lane_off;
             const float re[4] = {zr[c][0], zr[c][1], zr[c][2], zr[c][3]};
             const float im[4] = {zi[c][0], zi[c][1], zi[c][2], zi[c][3]};
             float ur[4], ui[4];
@@ -736,8 +742,14 @@ __global__ __launch_bounds__(256, 4) void band_synth_mfma_kernel(HilbertArgs a)
                     ui[v] = in ? ui[v] : 0.0f;
                 }
             }
-            store4<MODE>(dst, g.plane_bytes, ur, ui);
+            store4<MODE, float, true>((uint8_t *)g.u + boff[c] + lane_off, g.plane_bytes, ur, ui);
         }
+    };
+    for (int r0 = rfirst; r0 < r_end; r0 += 64) {  // wave-uniform bounds
+        group(r0, ya, yb);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            ya[s] = yb[s];
     }
 }
 

@@ -47,7 +47,8 @@ __device__ inline void unit_phasor4(const float (&re)[4], const float (&im)[4], 
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const float n2 = fmaf(re[v], re[v], im[v] * im[v]);
-        all_ok = all_ok && n2 >= 0x1p-120f && n2 <= 0x1p120f;
+        // 2^-120 <= n2 <= 2^120 as one unsigned test on the bits (NaN and 0 fail)
+        all_ok = all_ok && __float_as_uint(n2) - 0x03800000u <= 0x78000000u;
         const float inv = __builtin_amdgcn_rsqf(n2);
         ur[v] = re[v] * inv;
         ui[v] = im[v] * inv;
@@ -93,24 +94,33 @@ __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0
 // Stores 4 consecutive phasors (ur[v], ui[v]) of one row at `dst` in the
 // operand format of `MODE` (dst points at sample s0 of plane 0; the split
 // mode's lo plane is plane_bytes further).
-template <int MODE, class R>
+// One 16-byte store, streaming (non-temporal) when NT: the caller's planes
+// are read back only by a later kernel, long after they have left the cache.
+template <bool NT, class V>
+__device__ inline void st16(uint8_t *dst, V v)
+{
+    auto p = (PLV_GLOBAL V *)gptr(dst);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <int MODE, class R, bool NT = false>
 __device__ inline void store4(uint8_t *dst, int64_t plane_bytes, const R (&ur)[4], const R (&ui)[4])
 {
     if constexpr (MODE == M_F64) {
-        auto d = (PLV_GLOBAL vd2 *)gptr(dst);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            d[v] = vd2{(double)ur[v], (double)ui[v]};
+            st16<NT>(dst + 16 * v, vd2{(double)ur[v], (double)ui[v]});
     } else if constexpr (MODE == M_F32) {
-        auto d = (PLV_GLOBAL vf4 *)gptr(dst);
-        d[0] = vf4{(float)ur[0], (float)ui[0], (float)ur[1], (float)ui[1]};
-        d[1] = vf4{(float)ur[2], (float)ui[2], (float)ur[3], (float)ui[3]};
+        st16<NT>(dst, vf4{(float)ur[0], (float)ui[0], (float)ur[1], (float)ui[1]});
+        st16<NT>(dst + 16, vf4{(float)ur[2], (float)ui[2], (float)ur[3], (float)ui[3]});
     } else if constexpr (MODE == M_BF16) {
-        *(PLV_GLOBAL vu4 *)gptr(dst) = vu4{pack_bf16(ur[0], ui[0]), pack_bf16(ur[1], ui[1]), pack_bf16(ur[2], ui[2]),
-                                          pack_bf16(ur[3], ui[3])};
+        st16<NT>(dst, vu4{pack_bf16(ur[0], ui[0]), pack_bf16(ur[1], ui[1]), pack_bf16(ur[2], ui[2]),
+                          pack_bf16(ur[3], ui[3])});
     } else if constexpr (MODE == M_F16) {
-        *(PLV_GLOBAL vu4 *)gptr(dst) =
-            vu4{pack_f16(ur[0], ui[0]), pack_f16(ur[1], ui[1]), pack_f16(ur[2], ui[2]), pack_f16(ur[3], ui[3])};
+        st16<NT>(dst, vu4{pack_f16(ur[0], ui[0]), pack_f16(ur[1], ui[1]), pack_f16(ur[2], ui[2]), pack_f16(ur[3], ui[3])});
     } else {  // M_SPLIT: hi = rn(u), lo = rn(u - hi); u - hi is exact in FP32
         uint32_t hw[4], lw[4];
 #pragma unroll
@@ -118,8 +128,8 @@ __device__ inline void store4(uint8_t *dst, int64_t plane_bytes, const R (&ur)[4
             hw[v] = pack_bf16(ur[v], ui[v]);
             lw[v] = pack_bf16(ur[v] - bf16_lo(hw[v]), ui[v] - bf16_hi(hw[v]));
         }
-        *(PLV_GLOBAL vu4 *)gptr(dst) = vu4{hw[0], hw[1], hw[2], hw[3]};
-        *(PLV_GLOBAL vu4 *)gptr(dst + plane_bytes) = vu4{lw[0], lw[1], lw[2], lw[3]};
+        st16<NT>(dst, vu4{hw[0], hw[1], hw[2], hw[3]});
+        st16<NT>(dst + plane_bytes, vu4{lw[0], lw[1], lw[2], lw[3]});
     }
 }
 
