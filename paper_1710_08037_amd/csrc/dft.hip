@@ -98,8 +98,8 @@ __global__ __launch_bounds__(256) void dft_bins_kernel(HilbertArgs a)
         const int ts = min(c0 + lane, t - 1);
         cn = c0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            xn[i] = xbase[(int64_t)min(rw + i, hp.n - 1) * hp.ld + ts];
+        for (int i = 0; i < 16; ++i)  // read once: streaming loads
+            xn[i] = __builtin_nontemporal_load(&xbase[(int64_t)min(rw + i, hp.n - 1) * hp.ld + ts]);
     };
     auto stage_chunk = [&]() {  // this wave's tile; its own later reads see it
         const bool tin = cn + lane < t;

@@ -527,13 +527,18 @@ static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const pl
             fj[nj++] = FirJob{l.t, bands[b].fir_order / 2, (const double *)(ws + plan.fir_r_off[b]),
                               ws + l.firw_off[b]};
     }
+    // a length whose rows all take the DFT-bins kernel needs only its roots
+    std::vector<char> len_fft(plan.lens.size(), 0);
+    for (size_t q = 0; q < nprob; ++q)
+        if (!by_dft[q])
+            len_fft[plan.fft[q].len_index] = 1;
     for (size_t c = 0; c < plan.lens.size(); ++c) {
         const LenPlan &l = plan.lens[c];
         const size_t ti = std::find(plan.tw_logm.begin(), plan.tw_logm.end(), l.logm) - plan.tw_logm.begin();
         ChirpJob j{};
         j.t = l.t;
         j.logm = l.logm;
-        j.blue = l.blue ? 1 : 0;
+        j.blue = l.blue && len_fft[c] ? 1 : 0;
         j.chirp = l.blue ? ws + l.chirp_off : nullptr;
         j.bhat = l.blue ? ws + l.bhat_off : nullptr;
         j.roots = ws + l.roots_off;
@@ -543,12 +548,17 @@ static void fill_fft_tables(const Plan &plan, const plv_problem *probs, const pl
 }
 
 // Twiddle tables per FFT size, then the per-length set-up jobs, one launch
-// per size (the jobs are ordered by size).
-static hipError_t launch_fft_setup(const Plan &plan, uint8_t *ws, hipStream_t s, int &launches)
+// per size (the jobs are ordered by size).  With class_count, a size none of
+// whose rows takes a transform gets no twiddle table (its lengths' jobs then
+// write only their roots).
+static hipError_t launch_fft_setup(const Plan &plan, uint8_t *ws, hipStream_t s, int &launches,
+                                   const std::vector<int> *class_count = nullptr)
 {
     const bool f64 = plan.mode == M_F64;
     hipError_t e;
     for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
+        if (class_count && (*class_count)[c] == 0)
+            continue;
         if ((e = launch_twiddles(f64, ws + plan.tw_off[c], plan.tw_logm[c], s)) != hipSuccess)
             return e;
         ++launches;
@@ -610,7 +620,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
     if (real) {
         StageTimer tm(ctx, PLV_STAGE_HILBERT, s);
         int nl = 0;
-        if ((e = launch_fft_setup(plan, ws, s, nl)) != hipSuccess)
+        if ((e = launch_fft_setup(plan, ws, s, nl, &class_count)) != hipSuccess)
             return hip_fail(ctx, e, "FFT set-up kernel launch");
         tm.launched(nl);
         for (size_t c = 0; c < plan.tw_logm.size(); ++c) {
