@@ -883,8 +883,9 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_kernel(HilbertArgs a, int
 // (h_b real), so dL/dx = Re(sum_b M_b zbar_b) = Re(IDFT(sum_b h_b .*
 // DFT(zbar_b))), zbar_b being 0 outside the window.  With several bands the
 // running spectrum sum is kept in the work-group's slot of M elements (each
-// thread reading back only what it wrote), not in registers.
-template <class R, int LOGM, bool FIR>
+// thread reading back only what it wrote), not in registers.  ONE: calls
+// with a single band (no sum, no slot code).
+template <class R, int LOGM, bool ONE, bool FIR>
 __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArgs a)
 {
     constexpr int M = 1 << LOGM, PER = per_of(LOGM), NTA = nta_of(LOGM);
@@ -899,7 +900,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
     for (int ri = blockIdx.x; ri < a.nrows; ri += gridDim.x) {
         const RowRef rr = a.rows[ri];
         const HilbertProb hp = a.hp[rr.prob];
-        const int t = hp.t, nb = hp.nbands;
+        const int t = hp.t, nb = ONE ? 1 : hp.nbands;
         const cx<R> *ch = (const cx<R> *)hp.chirp;
         const cx<R> *bh = (const cx<R> *)hp.bhat;
         const int tid0 = act ? tid : 0;
@@ -942,7 +943,7 @@ __global__ __launch_bounds__(nt_of(LOGM)) void hilbert_adjoint_kernel(HilbertArg
                 }
             }
             // the band sum: bands 0 .. nb - 2 into the slot, the last one added to it in v
-            if (nb > 1 && act) {
+            if (!ONE && nb > 1 && act) {
                 if (b == 0) {
 #pragma unroll
                     for (int e = 0; e < PER; ++e)
@@ -1015,12 +1016,18 @@ hipError_t launch_sized(int kind, int mode, const HilbertArgs *ha, const ChirpJo
             hilbert_kernel<R, LOGM, false><<<nwg, NT, 0, s>>>(*ha, mode);
         }
     } else {
-        if (ha->fir) {
-            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true>, NT, ha->nrows, cus, ha);
-            hilbert_adjoint_kernel<R, LOGM, true><<<nwg, NT, 0, s>>>(*ha);
+        if (ha->nbands == 1 && !ha->fir) {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true, false>, NT, ha->nrows, cus, ha);
+            hilbert_adjoint_kernel<R, LOGM, true, false><<<nwg, NT, 0, s>>>(*ha);
+        } else if (ha->nbands == 1) {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, true, true>, NT, ha->nrows, cus, ha);
+            hilbert_adjoint_kernel<R, LOGM, true, true><<<nwg, NT, 0, s>>>(*ha);
+        } else if (!ha->fir) {
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false, false>, NT, ha->nrows, cus, ha);
+            hilbert_adjoint_kernel<R, LOGM, false, false><<<nwg, NT, 0, s>>>(*ha);
         } else {
-            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false>, NT, ha->nrows, cus, ha);
-            hilbert_adjoint_kernel<R, LOGM, false><<<nwg, NT, 0, s>>>(*ha);
+            const int nwg = grid_for(hilbert_adjoint_kernel<R, LOGM, false, true>, NT, ha->nrows, cus, ha);
+            hilbert_adjoint_kernel<R, LOGM, false, true><<<nwg, NT, 0, s>>>(*ha);
         }
     }
     return hipGetLastError();
