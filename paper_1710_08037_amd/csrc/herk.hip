@@ -59,7 +59,10 @@ struct Ring {
     static constexpr int PL = planes_of(MODE);
     static constexpr int PANEL = BM * RB;          // one panel of one plane
     static constexpr int STAGE = PL * 2 * PANEL;   // A and B panels of every plane
-    static constexpr int NS = (MODE == M_SPLIT) ? 4 : 8;
+    // split at the 64-wide tile: three stages (48 KB), so three work-groups
+    // share a CU (short-K problems: the lookahead matters less than the
+    // other work-groups' loads in flight)
+    static constexpr int NS = (MODE == M_SPLIT) ? (TBM == 64 ? 3 : 4) : 8;
 };
 
 template <int MODE>
@@ -474,10 +477,10 @@ __device__ inline void fused_store(const GramDesc &d, int I, int J,
 }
 
 // Work-groups per CU the launch bounds ask for: the 64-wide tile of the
-// 16-bit and FP32 modes takes half the LDS ring and a quarter of the
-// accumulators, so two work-groups share a CU.
+// 16-bit and FP32 modes takes half the LDS ring (split: three eighths) and a
+// quarter of the accumulators, so two (split: three) work-groups share a CU.
 template <int MODE, int BM>
-constexpr int wg_per_cu() { return (BM == 64 && MODE != M_F64) ? 2 : 1; }
+constexpr int wg_per_cu() { return BM == 64 && MODE == M_SPLIT ? 3 : ((BM == 64 && MODE != M_F64) ? 2 : 1); }
 
 template <int MODE, int BM>
 __global__ __launch_bounds__(THREADS, (wg_per_cu<MODE, BM>())) void herk_kernel(HerkArgs args)
