@@ -83,3 +83,25 @@ def test_many_time_points_sampled():
     for tt in np.random.default_rng(4).choice(t, size=8, replace=False):
         ref = oracle.full_over_trials(exact(z, "split_bf16"), window=(int(tt), int(tt) + 1))
         compare({k: got[k][tt] for k in got}, {k: ref[k][0] for k in ref}, TOL["split_bf16"], "t=%d" % tt)
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
+@pytest.mark.parametrize("n,ntr", [(192, 64), (150, 33), (64, 16), (1, 5), (192, 65), (193, 40)])
+def test_small_problem_edges(prec, n, ntr):
+    """Row and trial counts at tile and stage boundaries (192 rows = three
+    64-wide tiles, 64 trials = four 16-sample stages) and just past them,
+    every element of every matrix, G included and left out."""
+    t = 6
+    z = trials(ntr, n, t, seed=synth.seed_for(7, 30 + n + ntr))
+    for want_g in (True, False):
+        out = plv_mod().over_trials(to_dev(z, prec), prec=prec, want_g=want_g)
+        torch.cuda.synchronize()
+        ref = oracle.full_over_trials(exact(z, prec))
+        if want_g:
+            check(out, ref, prec, "n=%d ntr=%d %s" % (n, ntr, prec))
+        else:
+            assert out["g"] is None
+            got = {k: v.cpu().numpy().astype(np.float64) for k, v in out.items() if v is not None}
+            for tt in range(t):
+                for k in ("plv", "iplv"):
+                    assert np.abs(got[k][tt] - ref[k][tt]).max() <= TOL[prec]
