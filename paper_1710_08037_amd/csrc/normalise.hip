@@ -91,7 +91,8 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
 // in time), keeps the unit phasors in LDS, then writes each time point's
 // planes with consecutive threads on 4-sample groups of one row and then on
 // rows, so a wave stores runs of 8 rows x 64 B of the stage-major planes.
-// Trials past ntr are written as 0 up to the padded length.
+// Trials past ntr are written as 0 up to the padded length (a multiple of 4,
+// not necessarily of 32: the last block's groups past it are not stored).
 struct TrialShape {
     static constexpr int TR = 8;   // signals per block
     static constexpr int KB = 32;  // trials (plane samples) per block
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(256) void trial_planes_kernel(TrialArgs a)
         const int item = q * 256 + t;
         const int kq = item % (KB / 4), r = (item / (KB / 4)) % TR, tau = item / (KB / 4 * TR);
         const int64_t i = i0 + r;
-        if (tau0 + tau >= a.ntp || i >= a.n)
+        if (tau0 + tau >= a.ntp || i >= a.n || k0 + kq * VEC >= a.tpad)
             continue;
         const cplx_t *src = tile + (tau * TR + r) * KB + ((kq ^ (tau & 7)) << 2);
         real_t ur[VEC], ui[VEC];
@@ -195,14 +196,14 @@ __global__ __launch_bounds__(256) void row_scale_kernel(ScaleArgs a)
 hipError_t launch_trial_planes(int mode, const TrialArgs &a, hipStream_t s)
 {
     constexpr int TR = TrialShape::TR, KB = TrialShape::KB;
-    if (a.tpad % KB != 0)
+    if (a.tpad % VEC != 0)
         return hipErrorInvalidValue;
     const int tt = mode == M_F64 ? 8 : 16;
     for (int64_t r0 = 0; r0 < a.n; r0 += (int64_t)MAX_GRID_Y * TR) {
         TrialArgs b = a;
         b.row0 = (int32_t)r0;
         const int64_t nblk = (a.n - r0 + TR - 1) / TR;
-        dim3 grid((a.ntp + tt - 1) / tt, (unsigned)std::min<int64_t>(MAX_GRID_Y, nblk), a.tpad / KB);
+        dim3 grid((a.ntp + tt - 1) / tt, (unsigned)std::min<int64_t>(MAX_GRID_Y, nblk), (a.tpad + KB - 1) / KB);
         switch (mode) {
         case M_F64: trial_planes_kernel<M_F64><<<grid, 256, 0, s>>>(b); break;
         case M_F32: trial_planes_kernel<M_F32><<<grid, 256, 0, s>>>(b); break;

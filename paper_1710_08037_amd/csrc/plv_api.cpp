@@ -325,8 +325,8 @@ plv_status plv_destroy(plv_ctx *ctx)
     return PLV_OK;
 }
 
-plv_status plv_workspace_size(const plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs,
-                              int64_t nprob, const plv_band *bands, int32_t nbands, size_t *bytes)
+static plv_status workspace_size(const plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs,
+                                 int64_t nprob, const plv_band *bands, int32_t nbands, size_t *bytes, bool unit_k)
 {
     if (!bytes)
         return PLV_ERR_INVALID_ARG;
@@ -334,7 +334,7 @@ plv_status plv_workspace_size(const plv_ctx *ctx, plv_op op, plv_prec prec, cons
     Plan plan;
     std::string why;
     plv_status st = make_plan(ctx ? ctx->cus : 256, ctx ? ctx->occ : nullptr, op, prec, probs, nprob, bands, nbands,
-                              plan, why, ctx ? &ctx->tune : nullptr);
+                              plan, why, ctx ? &ctx->tune : nullptr, unit_k);
     if (st != PLV_OK) {
         if (ctx)
             const_cast<plv_ctx *>(ctx)->err = why;
@@ -344,9 +344,17 @@ plv_status plv_workspace_size(const plv_ctx *ctx, plv_op op, plv_prec prec, cons
     return PLV_OK;
 }
 
+plv_status plv_workspace_size(const plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs,
+                              int64_t nprob, const plv_band *bands, int32_t nbands, size_t *bytes)
+{
+    return workspace_size(ctx, op, prec, probs, nprob, bands, nbands, bytes, false);
+}
+
 // Shared front half of the compute entry points: checks, plan, device.
+// `unit_k` as in make_plan.
 static plv_status begin(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
-                        const plv_band *bands, int32_t nbands, void *ws, size_t ws_bytes, Plan &plan)
+                        const plv_band *bands, int32_t nbands, void *ws, size_t ws_bytes, Plan &plan,
+                        bool unit_k = false)
 {
     if (!ctx)
         return PLV_ERR_INVALID_ARG;
@@ -354,7 +362,8 @@ static plv_status begin(plv_ctx *ctx, plv_op op, plv_prec prec, const plv_proble
     if (ctx->device < 0)
         return fail(ctx, PLV_ERR_INVALID_ARG, "host-only context cannot compute");
     std::string why;
-    plv_status st = make_plan(ctx->cus, ctx->occ, op, prec, probs, nprob, bands, nbands, plan, why, &ctx->tune);
+    plv_status st =
+        make_plan(ctx->cus, ctx->occ, op, prec, probs, nprob, bands, nbands, plan, why, &ctx->tune, unit_k);
     if (st != PLV_OK)
         return fail(ctx, st, "%s", why.c_str());
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
@@ -896,8 +905,8 @@ plv_status plv_trials_workspace_size(const plv_ctx *ctx, plv_prec prec, const pl
     std::string why;
     plv_status st = trials_problems(p, prec, probs, why);
     if (st == PLV_OK)
-        return plv_workspace_size(ctx, PLV_OP_FROM_ANALYTIC, prec, probs.data(), (int64_t)probs.size(), nullptr, 1,
-                                  bytes);
+        return workspace_size(ctx, PLV_OP_FROM_ANALYTIC, prec, probs.data(), (int64_t)probs.size(), nullptr, 1, bytes,
+                              true);
     if (ctx)
         const_cast<plv_ctx *>(ctx)->err = why;
     return st;
@@ -915,7 +924,7 @@ plv_status plv_over_trials(plv_ctx *ctx, plv_prec prec, const plv_trials *p, voi
         return fail(ctx, st, "%s", why.c_str());
     Plan plan;
     st = begin(ctx, PLV_OP_FROM_ANALYTIC, prec, probs.data(), (int64_t)probs.size(), nullptr, 1, ws, ws_bytes,
-               plan);
+               plan, true);
     if (st != PLV_OK)
         return st;
     return enqueue_forward(ctx, plan, probs.data(), nullptr, 1, 0.0, (uint8_t *)ws, (hipStream_t)stream, p);

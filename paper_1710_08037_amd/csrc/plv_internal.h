@@ -2,8 +2,9 @@
 //
 // Layout of the phasor planes U in the workspace (one "Gram problem" = one
 // problem x band): chunk blocks, stage-major inside.  The window, rounded up
-// to tpad (a multiple of PLV_KGRAN samples, zero-filled beyond the window:
-// padding adds nothing to G), is cut into K-chunks of `chunk` samples; chunk
+// to tpad (a multiple of PLV_KGRAN samples, or of k_unit for a problem that
+// the planner keeps in one chunk; zero-filled beyond the window: padding adds
+// nothing to G), is cut into K-chunks of `chunk` samples; chunk
 // c of every row is stored together as one block of interleaved complex
 // phasors u = z/|z| (Eq. 4), blocks cstride bytes apart.  Inside a block the
 // samples go in 64-byte stages, all npad rows of one stage back to back
@@ -75,6 +76,13 @@ __host__ __device__ constexpr int tile_of(int mode) { return mode == M_F64 ? 64 
 // Bytes per complex phasor element in one plane.
 __host__ __device__ constexpr int cbytes_of(int mode) { return mode == M_F64 ? 16 : (mode == M_F32 ? 8 : 4); }
 __host__ __device__ constexpr int planes_of(int mode) { return mode == M_SPLIT ? 2 : 1; }
+// Samples of one K-unit of the Gram kernel: a 64-byte stage per plane row
+// (16 / 8 / 4 samples), two stages for plain BF16 and FP16, whose unit is one
+// 32-sample step of each of two MFMA chains.  A chunk's length is a multiple of it.
+__host__ __device__ constexpr int k_unit(int mode)
+{
+    return (mode == M_BF16 || mode == M_F16) ? 32 : 64 / cbytes_of(mode);
+}
 
 // One Gram problem: G = U U^H / t over its own phasor planes.
 struct GramDesc {
@@ -86,7 +94,8 @@ struct GramDesc {
     int32_t ntile;        // tiles per side = npad / bm
     int32_t nupper;       // tiles with I <= J = ntile (ntile + 1) / 2
     int32_t nchunk;       // K-chunks over tpad
-    int32_t chunk;        // samples per chunk (multiple of PLV_KGRAN); last may be shorter
+    int32_t chunk;        // samples per chunk (multiple of PLV_KGRAN, or of k_unit when there is
+                          // one chunk); last may be shorter
     int32_t nslot;        // partial slots (chunks per pass); passes = ceil(nchunk / nslot)
     int32_t fused;        // 1: one chunk, the Gram kernel stores the measures itself
     int32_t bm;           // tile edge BM of this problem (64 or 128; 64 in F64 mode)

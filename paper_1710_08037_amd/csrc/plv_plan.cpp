@@ -17,6 +17,17 @@ std::string msg(const char *fmt, long long a = 0, long long b = 0)
     return buf;
 }
 
+// A padded length off the PLV_KGRAN grid (make_plan's unit_k) is one chunk.
+bool single_chunk_k(GramPlan &g)
+{
+    if (g.tpad % PLV_KGRAN == 0)
+        return false;
+    g.chunk = g.tpad;
+    g.nchunk = 1;
+    g.nslot = 1;
+    return true;
+}
+
 // K-chunks of a problem computed alone.  Every (tile, chunk) item costs about
 // the same, so a pass takes ceil(items / slots) rounds of work-groups; the
 // chunk count is the one with the least estimated time (below), with no chunk
@@ -45,6 +56,8 @@ bool exact_split(int kgr, int nc)
 // exact split within the bounds.
 void choose_chunks_single(GramPlan &g, int slots, int bm, int maxc, int forced)
 {
+    if (single_chunk_k(g))
+        return;
     // Estimated time of a chunk count: for each pass, the rounds of work-groups
     // the GPU runs (items / slots, rounded up) times the length of one item,
     // its chunk plus a fixed per-item cost (prologue, fold, partial store) in
@@ -82,6 +95,8 @@ void choose_chunks_single(GramPlan &g, int slots, int bm, int maxc, int forced)
 // Inside a grouped launch every chunk of a problem has its own slot (one pass).
 void choose_chunks_grouped(GramPlan &g, int maxc)
 {
+    if (single_chunk_k(g))
+        return;
     const int kgr = g.tpad / PLV_KGRAN;
     const int per = std::min(kgr, maxc / PLV_KGRAN);
     g.chunk = per * PLV_KGRAN;
@@ -183,7 +198,8 @@ int tile_for(int mode, int64_t n, const Tuning *tune)
 }
 
 plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
-                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why, const Tuning *tune)
+                     const plv_band *bands, int32_t nbands, Plan &plan, std::string &why, const Tuning *tune,
+                     bool unit_k)
 {
     plan = Plan();
     if ((int)prec < 0 || (int)prec > 4) {
@@ -285,6 +301,12 @@ plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const pl
             g.t0 = (int)p.t0;
             g.t = (int)(t1 - p.t0);
             g.tpad = (g.t + PLV_KGRAN - 1) / PLV_KGRAN * PLV_KGRAN;
+            if (unit_k && !backward) {
+                const int ku = k_unit(mode);
+                const int tu = (g.t + ku - 1) / ku * ku;
+                if (tu <= MAX_CHUNK)
+                    g.tpad = tu;  // one chunk (single_chunk_k)
+            }
             g.ntile = g.npad / bm;
             g.nupper = g.ntile * (g.ntile + 1) / 2;
             const size_t nn = (size_t)p.n * (size_t)p.n;

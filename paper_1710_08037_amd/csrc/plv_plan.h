@@ -112,10 +112,14 @@ int model_tile(int mode, int64_t n);
 int tile_for(int mode, int64_t n, const Tuning *tune);
 
 // Checks the arguments and lays out the workspace.  `occ` (NOCC entries, see
-// occ_index) may be NULL: then 1 is assumed.
+// occ_index) may be NULL: then 1 is assumed.  `unit_k`: pad each problem's
+// samples only to the Gram kernel's K-unit of its mode (k_unit) rather than
+// to PLV_KGRAN, when that fits one K-chunk; such a problem runs as a single
+// chunk.  Used for the problems across trials, whose K (the trial count) is
+// a few dozen, where the granule would add up to 31 zero samples to each.
 plv_status make_plan(int cus, const int *occ, plv_op op, plv_prec prec, const plv_problem *probs, int64_t nprob,
                      const plv_band *bands, int32_t nbands, Plan &plan, std::string &why,
-                     const Tuning *tune = nullptr);
+                     const Tuning *tune = nullptr, bool unit_k = false);
 
 // The K-chunk counts a single-problem plan can take (every chunk but the last
 // the same whole number of granules), ascending; empty for a grouped plan.

@@ -163,3 +163,26 @@ def test_workspace_follows_the_tile_edge(host_ctx):
     assert st == 0
     planes = 2 * 64 * 1024 * 8  # 64 more padded rows per problem
     assert planes - 4096 <= b - a <= planes  # less the smaller item table
+
+
+def _trials_ws(ctx, prec, n, ntr, ntp=100):
+    t = _abi.Trials(n, ntr, ntp, ntp, n * ntp, 1, 0, 0, 4096, 4096, 4096, 4096, 0)
+    out = C.c_size_t(0)
+    assert _abi.lib().plv_trials_workspace_size(ctx, _abi.PREC[prec], C.byref(t), C.byref(out)) == 0
+    return out.value
+
+
+def test_trials_pad_k_to_the_mode_unit(host_ctx):
+    """Across trials the contracted length is the trial count (Eq. 8), a few
+    dozen: the planes are padded only to the Gram kernel's K-unit of the mode
+    (split BF16 16 samples, BF16 and FP16 32, FP32 8, FP64 4), so a count
+    shares its workspace with the next multiple of that unit and needs less
+    than the next multiple of 32 where the unit is smaller."""
+    ws = lambda prec, ntr: _trials_ws(host_ctx, prec, 148, ntr)
+    assert ws("split_bf16", 40) == ws("split_bf16", 48) < ws("split_bf16", 64)
+    assert ws("split_bf16", 33) == ws("split_bf16", 48)
+    assert ws("bf16", 40) == ws("bf16", 64) == ws("bf16", 33)
+    assert ws("f16", 40) == ws("f16", 64)
+    assert ws("f32", 40) < ws("f32", 48) < ws("f32", 64)
+    assert ws("f64", 40) < ws("f64", 44) < ws("f64", 64)
+    assert ws("f64", 41) == ws("f64", 44)

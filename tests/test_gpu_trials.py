@@ -85,12 +85,14 @@ def test_many_time_points_sampled():
         compare({k: got[k][tt] for k in got}, {k: ref[k][0] for k in ref}, TOL["split_bf16"], "t=%d" % tt)
 
 
-@pytest.mark.parametrize("prec", ["split_bf16", "bf16", "f16"])
-@pytest.mark.parametrize("n,ntr", [(192, 64), (150, 33), (64, 16), (1, 5), (192, 65), (193, 40)])
+@pytest.mark.parametrize("prec", ["f64", "f32", "split_bf16", "bf16", "f16"])
+@pytest.mark.parametrize("n,ntr", [(192, 64), (150, 33), (64, 16), (1, 5), (192, 65), (193, 40), (70, 48), (100, 9)])
 def test_small_problem_edges(prec, n, ntr):
     """Row and trial counts at tile and stage boundaries (192 rows = three
-    64-wide tiles, 64 trials = four 16-sample stages) and just past them,
-    every element of every matrix, G included and left out."""
+    64-wide tiles, 48 and 64 trials = three and four 16-sample stages) and
+    just past them, every element of every matrix, G included and left out.
+    The trials are padded only to the mode's K-unit (4, 8, 16 or 32), so
+    most counts here end inside the last 32-trial block of the transpose."""
     t = 6
     z = trials(ntr, n, t, seed=synth.seed_for(7, 30 + n + ntr))
     for want_g in (True, False):
