@@ -117,6 +117,47 @@ __device__ inline void store_one(const GramDesc &d, int64_t idx, bool diag, bool
     }
 }
 
+// One entry's outputs as store_one writes them, for a four-entry store: the
+// measures (diagonal: 1, 0, 0) and G's components (Im negated for a
+// mirrored entry), placed at position q of each vector.
+template <int MODE>
+__device__ inline void entry_of(bool diag, bool conj, double r, double m, int q, vf4 &vp, vf4 &vi, vf4 &vc,
+                                vf4 &g01, vf4 &g23)
+{
+    static_assert(MODE != M_F64, "FP32 outputs only");
+    float p = 1.0f, i = 0.0f, c = 0.0f;
+    if (!diag)
+        measures<MODE>(r, m, p, i, c);
+    vp[q] = p;
+    vi[q] = i;
+    vc[q] = c;
+    const float gr = (float)r, gi = conj ? (float)(-m) : (float)m;
+    vf4 &g = q < 2 ? g01 : g23;
+    g[2 * (q & 1)] = gr;
+    g[2 * (q & 1) + 1] = gi;
+}
+
+// Four consecutive entries idx .. idx + 3 of one output row (entry_of):
+// idx a multiple of 4 and every output 16-byte aligned, so each output takes
+// one 16-byte store (G two) in place of four 4-byte ones -- the vector-memory
+// path takes a 64-lane store in about the same time whether a lane writes 4
+// or 16 bytes.
+__device__ inline void store_four(const GramDesc &d, int64_t idx, const vf4 &vp, const vf4 &vi, const vf4 &vc,
+                                  const vf4 &g01, const vf4 &g23)
+{
+    if (d.plv)
+        *(PLV_GLOBAL vf4 *)(gptr((float *)d.plv) + idx) = vp;
+    if (d.iplv)
+        *(PLV_GLOBAL vf4 *)(gptr((float *)d.iplv) + idx) = vi;
+    if (d.ciplv)
+        *(PLV_GLOBAL vf4 *)(gptr((float *)d.ciplv) + idx) = vc;
+    if (d.g) {
+        auto g = (PLV_GLOBAL vf4 *)(gptr((float *)d.g) + 2 * idx);
+        g[0] = g01;
+        g[1] = g23;
+    }
+}
+
 // r, m: Re and Im of G_ij (already divided by T); gi <= gj < d.n.
 template <int MODE>
 __device__ inline void store_entry(const GramDesc &d, int64_t gi, int64_t gj, double r, double m)

@@ -85,16 +85,18 @@ __global__ __launch_bounds__(256) void normalise_kernel(NormArgs a)
 }
 
 // Across trials: a transpose through LDS.  A block covers TT consecutive
-// time points x TR consecutive signals x 32 consecutive trials (one sample
-// granule of the planes).  It reads z(k, i, t0 + tau) with consecutive threads
-// on consecutive time points (whole 128-byte runs when samples are contiguous
-// in time), keeps the unit phasors in LDS, then writes each time point's
-// planes with consecutive threads on 4-sample groups of one row and then on
-// rows, so a wave stores runs of 8 rows x 64 B of the stage-major planes.
-// Trials past ntr are written as 0 up to the padded length (a multiple of 4,
-// not necessarily of 32: the last block's groups past it are not stored).
+// time points x TR consecutive signals x 32 consecutive trials.  It reads
+// z(k, i, t0 + tau) with consecutive threads on consecutive time points
+// (512-byte runs when samples are contiguous in time: the reads, strided
+// over signals and trials, set the kernel's time, and runs of 128 B over
+// 8 signals were 6% slower), keeps the unit phasors in LDS, then writes each
+// time point's planes with consecutive threads on 4-sample groups of one row
+// and then on rows, so a wave stores runs of TR rows x 64 B of the
+// stage-major planes.  Trials past ntr are written as 0 up to the padded
+// length (a multiple of 4, not necessarily of 32: the last block's groups
+// past it are not stored).
 struct TrialShape {
-    static constexpr int TR = 8;   // signals per block
+    static constexpr int TR = 2;   // signals per block
     static constexpr int KB = 32;  // trials (plane samples) per block
 };
 
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(256) void trial_planes_kernel(TrialArgs a)
     typedef typename std::conditional<MODE == M_F64, double, float>::type real_t;
     typedef typename std::conditional<MODE == M_F64, vd2, vf2>::type cplx_t;
     constexpr int TR = TrialShape::TR, KB = TrialShape::KB;
-    constexpr int TT = MODE == M_F64 ? 8 : 16;      // time points per block
+    constexpr int TT = MODE == M_F64 ? 32 : 64;     // time points per block
     constexpr int NLD = TT * TR * KB / 256;         // loads per thread
     constexpr int NST = TT * TR * (KB / 4) / 256;   // 4-sample stores per thread
     // [tau][r][k], the 4-trial group of k swizzled by tau so that both the
@@ -198,7 +200,7 @@ hipError_t launch_trial_planes(int mode, const TrialArgs &a, hipStream_t s)
     constexpr int TR = TrialShape::TR, KB = TrialShape::KB;
     if (a.tpad % VEC != 0)
         return hipErrorInvalidValue;
-    const int tt = mode == M_F64 ? 8 : 16;
+    const int tt = mode == M_F64 ? 32 : 64;
     for (int64_t r0 = 0; r0 < a.n; r0 += (int64_t)MAX_GRID_Y * TR) {
         TrialArgs b = a;
         b.row0 = (int32_t)r0;
