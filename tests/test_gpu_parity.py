@@ -230,6 +230,37 @@ def test_input_rows_off_a_16_byte_boundary():
         compare(h, o, TOL[prec], "offset view %s" % prec)
 
 
+def test_outputs_off_a_16_byte_boundary():
+    """Outputs 4 bytes (G 8 bytes) past a 16-byte boundary, given through the
+    C ABI: a single-chunk problem's fused store then writes entry by entry
+    instead of four entries per 16-byte store, with bit-identical results."""
+    import ctypes as C
+
+    from paper_1710_08037_amd import _abi, api
+    n, t = 148, 200   # n a multiple of 4; T < 256 keeps one K-chunk, so the tile stores its measures
+    z = synth.glag_analytic(n, t, 1000.0, 8, (8.0, 12.0), seed=synth.seed_for(2, 41), dtype=np.complex64)
+    zd = torch.from_numpy(z).cuda()
+    for prec in ("split_bf16", "f32"):
+        ref = plv_mod().from_analytic(zd, prec=prec, want_g=True)
+        outs = {k: torch.zeros(n * n + 4, dtype=torch.float32, device="cuda")[1:1 + n * n]
+                for k in ("plv", "iplv", "ciplv")}
+        outs["g"] = torch.zeros(n * n + 2, dtype=torch.complex64, device="cuda")[1:1 + n * n]
+        assert all(o.data_ptr() % 16 != 0 for o in outs.values())
+        p = _abi.PREC[prec]
+        arr = _abi.problems([_abi.Problem(n, t, t, 0, 0, zd.data_ptr(),
+                                          *(outs[k].data_ptr() for k in ("plv", "iplv", "ciplv", "g")))])
+        ctx = api.context(zd.device)
+        ws = api._workspace(ctx, _abi.OP_FROM_ANALYTIC, p, arr, None, 1, zd.device)
+        _abi.check(_abi.lib().plv_from_analytic(ctx.handle, p, arr, 1, C.c_void_p(ws.data_ptr()), ws.numel(),
+                                                api._stream(zd.device)), ctx.handle)
+        torch.cuda.synchronize()
+        for k in ("plv", "iplv", "ciplv", "g"):
+            assert torch.equal(outs[k].view(n, n), ref[k]), (prec, k)
+        o = oracle.full_from_analytic(exact_input(z, prec))
+        h = {k: v.view(n, n).cpu().numpy().astype(np.complex128 if k == "g" else np.float64) for k, v in outs.items()}
+        compare(h, o, TOL[prec], "offset outputs %s" % prec)
+
+
 @pytest.mark.parametrize("prec", ["f32", "split_bf16", "f64"])
 def test_many_tiles_many_chunks_sampled_pairs(prec):
     """N = 2000 signals (16 tiles a side, 8 for FP64's smaller tiles: the
