@@ -463,7 +463,7 @@ __device__ inline void fused_store(const GramDesc &d, int I, int J,
         // inside n or all outside, and stores them at once (store_four).  On
         // 148 signals x 40 trials x 4000 time points the Gram took 0.455 ms
         // with one 4-byte store per entry and takes 0.411 ms so (0.143 ms
-        // with no store at all: 1.05 GB of output at partial cache lines).  A
+        // with no store at all: writing the 1.05 GB of output is most of it).  A
         // diagonal tile is one pass over its square, the entries below its
         // diagonal taken from the conjugate of their mirror, so no group
         // straddles the diagonal; an off-diagonal tile writes block (I, J)
