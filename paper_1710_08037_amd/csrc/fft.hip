@@ -1074,21 +1074,35 @@ namespace {
 
 // |H(e^{i theta})|^2 = A(theta)^2, A = c_0 + 2 sum_{j=1..half} c_j cos(j theta),
 // theta = 2 pi k / t, by Clenshaw's recurrence in FP64 (no trigonometry inside
-// the sum).
+// the sum).  One thread per bin; the coefficients, the same for every thread,
+// go through LDS in runs of FIR_RUN, taken from the top as the recurrence
+// runs (read from global memory at every step, the 2000th-order band's
+// weights took 88 us at t = 8192).
+constexpr int FIR_RUN = 1024;
 template <class R>
 __global__ __launch_bounds__(256) void fir_weights_kernel(const FirJob *jobs)
 {
+    __shared__ double cr[FIR_RUN];
     const FirJob j = jobs[blockIdx.y];
+    if (2 * (int)blockIdx.x * 256 > j.t)
+        return;  // every bin of the work-group is past t / 2 (before any barrier)
     const int k = blockIdx.x * 256 + threadIdx.x;
-    if (2 * k > j.t)
-        return;
     const double cs = cospi(2.0 * (double)k / (double)j.t);
     double b1 = 0.0, b2 = 0.0;
-    for (int m = j.half; m >= 1; --m) {
-        const double b0 = j.c[m] + 2.0 * cs * b1 - b2;
-        b2 = b1;
-        b1 = b0;
+    for (int top = j.half; top >= 1; top -= FIR_RUN) {  // coefficients lo .. top
+        const int lo = max(1, top - FIR_RUN + 1);
+        __syncthreads();  // the previous run has been read
+        for (int i = threadIdx.x; i <= top - lo; i += 256)
+            cr[i] = j.c[lo + i];
+        __syncthreads();
+        for (int m = top; m >= lo; --m) {
+            const double b0 = cr[m - lo] + 2.0 * cs * b1 - b2;
+            b2 = b1;
+            b1 = b0;
+        }
     }
+    if (2 * k > j.t)
+        return;
     const double amp = j.c[0] + 2.0 * (b1 * cs - b2);  // b1 cos - b2 = sum_{m>=1} c_m cos(m theta)
     ((R *)j.w)[k] = (R)(amp * amp);
 }
