@@ -1073,38 +1073,42 @@ hipError_t launch_twiddles(bool f64, void *tab, int logm, hipStream_t s)
 namespace {
 
 // |H(e^{i theta})|^2 = A(theta)^2, A = c_0 + 2 sum_{j=1..half} c_j cos(j theta),
-// theta = 2 pi k / t, by Clenshaw's recurrence in FP64 (no trigonometry inside
-// the sum).  One thread per bin; the coefficients, the same for every thread,
-// go through LDS in runs of FIR_RUN, taken from the top as the recurrence
-// runs (read from global memory at every step, the 2000th-order band's
-// weights took 88 us at t = 8192).
-constexpr int FIR_RUN = 1024;
+// theta = 2 pi k / t, in FP64.  FIR_LANES consecutive lanes share a bin, each
+// summing one run of the taps with cos(j theta) stepped by the three-term
+// recurrence cos((j+1) theta) = 2 cos(theta) cos(j theta) - cos((j-1) theta)
+// from two cosines of exactly reduced angles (2 k j mod 2t over t), then a
+// shuffle reduction: the 2000th-order band at t = 8192 is 4097 bins, and one
+// lane per bin (a 1000-step dependent chain) took 46 us in 17 work-groups.
+constexpr int FIR_LANES = 8;
 template <class R>
 __global__ __launch_bounds__(256) void fir_weights_kernel(const FirJob *jobs)
 {
-    __shared__ double cr[FIR_RUN];
     const FirJob j = jobs[blockIdx.y];
-    if (2 * (int)blockIdx.x * 256 > j.t)
-        return;  // every bin of the work-group is past t / 2 (before any barrier)
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    const double cs = cospi(2.0 * (double)k / (double)j.t);
-    double b1 = 0.0, b2 = 0.0;
-    for (int top = j.half; top >= 1; top -= FIR_RUN) {  // coefficients lo .. top
-        const int lo = max(1, top - FIR_RUN + 1);
-        __syncthreads();  // the previous run has been read
-        for (int i = threadIdx.x; i <= top - lo; i += 256)
-            cr[i] = j.c[lo + i];
-        __syncthreads();
-        for (int m = top; m >= lo; --m) {
-            const double b0 = cr[m - lo] + 2.0 * cs * b1 - b2;
-            b2 = b1;
-            b1 = b0;
+    const int k = (blockIdx.x * 256 + threadIdx.x) / FIR_LANES, part = threadIdx.x % FIR_LANES;
+    if (2 * k > j.t)
+        return;  // past t / 2: the bin's FIR_LANES lanes all leave (the reduction stays within a bin)
+    const int per = (j.half + FIR_LANES - 1) / FIR_LANES;
+    const int lo = 1 + part * per, hi = min(j.half, lo + per - 1);
+    const int64_t t2 = 2 * (int64_t)j.t;
+    double acc = 0.0;
+    if (lo <= hi) {
+        double cm = cospi((double)((2 * (int64_t)k * lo) % t2) / (double)j.t);         // cos(lo theta)
+        double cp = cospi((double)((2 * (int64_t)k * (lo - 1)) % t2) / (double)j.t);   // cos((lo - 1) theta)
+        const double c2 = 2.0 * cospi((double)((2 * (int64_t)k) % t2) / (double)j.t);
+        for (int m = lo; m <= hi; ++m) {
+            acc = fma(j.c[m], cm, acc);
+            const double cn = fma(c2, cm, -cp);
+            cp = cm;
+            cm = cn;
         }
     }
-    if (2 * k > j.t)
-        return;
-    const double amp = j.c[0] + 2.0 * (b1 * cs - b2);  // b1 cos - b2 = sum_{m>=1} c_m cos(m theta)
-    ((R *)j.w)[k] = (R)(amp * amp);
+#pragma unroll
+    for (int off = FIR_LANES / 2; off >= 1; off >>= 1)
+        acc += __shfl_xor(acc, off, FIR_LANES);
+    if (part == 0) {
+        const double amp = j.c[0] + 2.0 * acc;
+        ((R *)j.w)[k] = (R)(amp * amp);
+    }
 }
 
 }  // namespace
@@ -1115,7 +1119,7 @@ hipError_t launch_fir_weights(bool f64, const FirJob *jobs, int njobs, int max_t
         return hipSuccess;
     if (njobs > 65535 || max_t < 1)
         return hipErrorInvalidValue;
-    dim3 grid((unsigned)((max_t / 2 + 1 + 255) / 256), (unsigned)njobs);
+    dim3 grid((unsigned)(((int64_t)(max_t / 2 + 1) * FIR_LANES + 255) / 256), (unsigned)njobs);
     if (f64)
         fir_weights_kernel<double><<<grid, 256, 0, s>>>(jobs);
     else
