@@ -40,6 +40,23 @@ def test_fir_bands_forward(prec, t):
         compare(to_np(out, b), ref, TOL[prec], "t=%d band %s %s" % (t, band, prec))
 
 
+@pytest.mark.parametrize("prec", ["f64", "split_bf16"])
+def test_short_fir_orders(prec):
+    """Orders 2, 6 and 14 (1, 3 and 7 taps past the centre: fewer than the
+    weight kernel's lanes per bin, so most lanes sum nothing) and 18 (9
+    taps: two per lane, the last lane one), in one call, against the oracle."""
+    n, t, fs = 12, 1024, 1000.0
+    bands = [(80.0, 160.0, 2), (80.0, 160.0, 6), (80.0, 160.0, 14), (80.0, 160.0, 18)]
+    win = (32, t - 32)
+    x = synth.glag_real(n, t, fs, 4, (90, 150), seed=731)
+    out = plv_mod().from_real(real_dev(x, prec), fs, bands=bands, prec=prec, window=win, want_g=True)
+    torch.cuda.synchronize()
+    xr = exact_real(x, prec)
+    for b, band in enumerate(bands):
+        ref = oracle.full_from_real(xr, fs, band, window=win)
+        compare(to_np(out, b), ref, TOL[prec], "short FIR band %s %s" % (band, prec))
+
+
 @pytest.mark.parametrize("prec", ["f32", "split_bf16"])
 def test_fir_batch_of_uneven_rows(prec):
     """Several problems of different lengths, each with an FIR band: one
