@@ -230,15 +230,18 @@ def test_input_rows_off_a_16_byte_boundary():
         compare(h, o, TOL[prec], "offset view %s" % prec)
 
 
-def test_outputs_off_a_16_byte_boundary():
+@pytest.mark.parametrize("t", [200, 3000])
+def test_outputs_off_a_16_byte_boundary(t):
     """Outputs 4 bytes (G 8 bytes) past a 16-byte boundary, given through the
-    C ABI: a single-chunk problem's fused store then writes entry by entry
-    instead of four entries per 16-byte store, with bit-identical results."""
+    C ABI: the measures are then written entry by entry instead of four
+    entries per 16-byte store -- by the Gram kernel's fused store (T = 200,
+    one K-chunk) or by the epilogue (T = 3000, several chunks) -- with
+    bit-identical results."""
     import ctypes as C
 
     from paper_1710_08037_amd import _abi, api
-    n, t = 148, 200   # n a multiple of 4; T < 256 keeps one K-chunk, so the tile stores its measures
-    z = synth.glag_analytic(n, t, 1000.0, 8, (8.0, 12.0), seed=synth.seed_for(2, 41), dtype=np.complex64)
+    n = 148   # a multiple of 4, so aligned outputs take the four-entry stores
+    z = synth.glag_analytic(n, t, 1000.0, 8, (8.0, 12.0), seed=synth.seed_for(2, 41 + t), dtype=np.complex64)
     zd = torch.from_numpy(z).cuda()
     for prec in ("split_bf16", "f32"):
         ref = plv_mod().from_analytic(zd, prec=prec, want_g=True)
