@@ -162,6 +162,24 @@ def test_grouped_batch_equals_single_calls(prec):
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "f32"])
+def test_grouped_multichunk_problems(prec):
+    """A grouped call whose long problems span two K-chunks (T = 20000 past
+    the 16384-sample chunk cap), so their sums go through the epilogue over
+    the launch's tile list with both tile edges present (68 rows on 64-wide
+    tiles, 360 on 128-wide), next to a single-chunk problem; every element
+    against the oracle."""
+    shapes = [(68, 20000), (360, 20000), (148, 900)]
+    zs = [synth.glag_analytic(n, t, 1000.0, 3, (8, 12), seed=synth.seed_for(2, 60 + k))
+          for k, (n, t) in enumerate(shapes)]
+    batch = plv_mod().from_analytic_batch([to_dev(z, prec) for z in zs], prec=prec, want_g=True)
+    torch.cuda.synchronize()
+    for k, z in enumerate(zs):
+        ref = oracle.full_from_analytic(exact_input(z, prec))
+        got = {kk: v.cpu().numpy().astype(np.complex128 if kk == "g" else np.float64) for kk, v in batch[k].items()}
+        compare(got, ref, TOL[prec], "grouped multi-chunk %d %s" % (k, prec))
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "f32"])
 def test_sensor_scale_workload_sampled_pairs(prec):
     """N = 1024 analytic signals of T = 60000 samples (1 kHz, 60 s), 32 latent
     8-12 Hz oscillators: the full-size workload, in the launch configuration
