@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void epilogue_kernel(EpiArgs args)
 }
 
 // Row-wise variant, for FP32 outputs with n a multiple of 4 and 16-byte
-// aligned outputs (not coherency): a work-group takes an ESB x ESB sub-block
+// aligned outputs: a work-group takes an ESB x ESB sub-block
 // of an upper tile, sums its slots into LDS (in index order, as
 // epilogue_kernel does, so the values are the same), then writes the
 // sub-block and its mirror row by row, four entries per 16-byte store
@@ -152,8 +152,14 @@ __global__ __launch_bounds__(256) void epilogue_rows_kernel(EpiArgs args)
             sr += part[c * cstride + idx];
             si += part[c * cstride + BM * BM + idx];
         }
-        lr[a][b] = sr * inv_t;
-        li[a][b] = si * inv_t;
+        if (args.coherence) {  // as epilogue_kernel: S_ij / sqrt(S_ii S_jj), 0 where a row is all zero
+            const double den = sqrt(d.diag[gi0 + a]) * sqrt(d.diag[gj0 + b]);
+            lr[a][b] = den > 0.0 ? sr / den : 0.0;
+            li[a][b] = den > 0.0 ? si / den : 0.0;
+        } else {
+            lr[a][b] = sr * inv_t;
+            li[a][b] = si * inv_t;
+        }
     }
     __syncthreads();
 
@@ -225,7 +231,7 @@ hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, int bm_max, b
     if (ntiles <= 0)
         return hipSuccess;
     if (rows) {
-        if (a.coherence || mode == M_F64)
+        if (mode == M_F64)
             return hipErrorInvalidValue;
         dim3 grid(ntiles, (bm_max / ESB) * (bm_max / ESB));
         switch (mode) {

@@ -591,11 +591,11 @@ static hipError_t launch_fft_setup(const Plan &plan, uint8_t *ws, hipStream_t s,
     return hipSuccess;
 }
 
-// The row-wise epilogue applies: FP32 outputs, not coherency, and every
-// problem's rows start 16-byte aligned (n a multiple of 4, aligned outputs).
-static bool rows_ok(int mode, const EpiArgs &ea, const GramDesc *gd, size_t ng)
+// The row-wise epilogue applies: FP32 outputs, and every problem's rows
+// start 16-byte aligned (n a multiple of 4, aligned outputs).
+static bool rows_ok(int mode, const GramDesc *gd, size_t ng)
 {
-    if (mode == M_F64 || ea.coherence)
+    if (mode == M_F64)
         return false;
     for (size_t q = 0; q < ng; ++q) {
         const uintptr_t al = (uintptr_t)gd[q].plv | (uintptr_t)gd[q].iplv | (uintptr_t)gd[q].ciplv | (uintptr_t)gd[q].g;
@@ -780,7 +780,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
             tm.launched();
             ea.coherence = true;
         }
-        if ((e = launch_epilogue(mode, ea, d.nupper, d.bm, rows_ok(mode, ea, &d, 1), s)) != hipSuccess)
+        if ((e = launch_epilogue(mode, ea, d.nupper, d.bm, rows_ok(mode, &d, 1), s)) != hipSuccess)
             return hip_fail(ctx, e, "epilogue kernel launch");
         tm.launched();
         return PLV_OK;
@@ -811,7 +811,7 @@ static plv_status enqueue_forward(plv_ctx *ctx, const Plan &plan, const plv_prob
         ea.coherence = true;
     }
     ea.tiles = (const TileRef *)(ws + plan.tile_off);
-    if ((e = launch_epilogue(mode, ea, (int)tiles.size(), plan.bm_max, rows_ok(mode, ea, gd.data(), gd.size()), s)) !=
+    if ((e = launch_epilogue(mode, ea, (int)tiles.size(), plan.bm_max, rows_ok(mode, gd.data(), gd.size()), s)) !=
         hipSuccess)
         return hip_fail(ctx, e, "epilogue kernel launch");
     tm.launched();

@@ -321,8 +321,8 @@ hipError_t launch_herk(int mode, int bm, const HerkArgs &a, int nwg, hipStream_t
 // Tile edges the Gram kernel has for a mode.
 bool tile_supported(int mode, int bm);
 // bm_max: the largest tile edge among the tiles (the grid covers it).  rows:
-// the row-wise kernel (FP32 outputs, no coherency, every problem with n a
-// multiple of 4 and 16-byte aligned outputs; the caller checks).
+// the row-wise kernel (FP32 outputs, every problem with n a multiple of 4
+// and 16-byte aligned outputs; the caller checks).
 hipError_t launch_epilogue(int mode, const EpiArgs &a, int ntiles, int bm_max, bool rows, hipStream_t s);
 hipError_t launch_row_scale(bool f64, const ScaleArgs &a, hipStream_t s);
 hipError_t launch_trial_planes(int mode, const TrialArgs &a, hipStream_t s);
